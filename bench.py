@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Throughput of the fused OReg D2Q9 sweep on one MI355X.
+
+One step = one sweep (pull streaming + moments + equilibrium + OReg
+reconstruction + relaxation + store) over the whole lattice.  Workload: the
+4096 x 4096 periodic lattice with the rotated (atan(1/2)) shear wave,
+u0 = 0.05, guided equilibrium, theta = 1/3, tau = 0.6, FP64 storage, one
+lattice per launch.  Populations are resident in HBM before timing starts.
+
+Prints one JSON line (rank 0):
+  value      MLUPS = nx * ny * steps / seconds / 1e6 (FP64 storage)
+  roofline   the sweep kernel's algorithmic bytes (2 * 9 * 8 per node) per
+             launch over its average launch time (HIP events on the lattice's
+             stream), against 8 TB/s; traffic from rocprofv3 counters when
+             profiles/ holds them for this kernel
+  variants   the same workload with shifted FP32 / FP16 / BF16 storage
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the workload
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (FP64 vs FP32/BF16 storage) at % HBM roofline; p50/p99 latency batched"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_NODE = {"f64": 144, "f32s": 72, "f16s": 36, "bf16s": 36}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_4096.json")
+
+
+def parse():
+    p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1000)
+    p.add_argument("--warmup", type=int, default=50)
+    p.add_argument("--n", type=int, default=4096, help="lattice side")
+    p.add_argument("--tau", type=float, default=0.6)
+    p.add_argument("--storage", default="f64", choices=sorted(BYTES_PER_NODE))
+    p.add_argument("--variants", default="f32s,f16s,bf16s",
+                   help="other storages to time on the same workload ('' for none)")
+    p.add_argument("--variant-steps", type=int, default=300)
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--cpu-steps", type=int, default=4,
+                   help="oracle steps on the full lattice for the CPU baseline")
+    return p.parse_args()
+
+
+def time_lattice(oreg, torch, n, tau, storage, steps, warmup, fields):
+    """Return (elapsed_ms, steps) of `steps` sweeps timed with HIP events on
+    the stream the sweep is launched on."""
+    stream = torch.cuda.current_stream()
+    rho0 = 1.0
+    with oreg.Lattice(n, n, tau, 1.0 / 3.0, storage=storage, rho0=rho0, stream=stream) as lat:
+        lat.init(*fields)
+        lat.step(warmup)
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        lat.step(steps)
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end)
+        diag = lat.diagnostics()
+    return ms, diag
+
+
+def load_traffic(storage, n, nbytes_alg):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    covers this kernel build; else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    entry = t.get("kernels", {}).get(storage)
+    if not entry or entry.get("n") != n or entry.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return entry.get("hbm_bytes_per_launch")
+
+
+def kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "d2q9.hpp"):
+        with open(os.path.join(ROOT, "paper_2501_16000_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(n, tau, steps, fields):
+    import numpy as np
+
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
+    f = oracle.init("guided", 1.0 / 3.0, *fields)
+    t0 = time.perf_counter()
+    f = oracle.run(f, steps, tau, 1.0 / 3.0, "guided", nthreads=threads)
+    dt = time.perf_counter() - t0
+    assert np.isfinite(f[0, 0, 0])
+    return {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
+            "sample": f"{n}x{n} rotated shear wave, FP64, guided, tau={tau}, {steps} steps "
+                      f"({dt:.1f} s, OpenMP over nodes)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the sweep's multi-GPU slab decomposition is design-only).", file=sys.stderr)
+        return 2
+    import torch
+
+    from paper_2501_16000_amd import oreg, workloads
+
+    torch.cuda.set_device(0)
+    n, tau = args.n, args.tau
+    fields = workloads.shear_wave(n, 0.05)
+    ms, diag = time_lattice(oreg, torch, n, tau, args.storage, args.steps, args.warmup, fields)
+    if diag[5] != 0:
+        raise RuntimeError("non-finite populations after the timed run")
+    cells = n * n
+    sec = ms / 1e3
+    mlups = cells * args.steps / sec / 1e6
+    per_launch_s = sec / args.steps
+    alg_bytes = BYTES_PER_NODE[args.storage] * cells
+    achieved = alg_bytes / per_launch_s / 1e9
+    traffic = load_traffic(args.storage, n, alg_bytes)
+
+    variants = {}
+    for st in [s for s in args.variants.split(",") if s and s != args.storage]:
+        vms, vdiag = time_lattice(oreg, torch, n, tau, st, args.variant_steps,
+                                  min(args.warmup, 20), fields)
+        vsec = vms / 1e3
+        v_ach = BYTES_PER_NODE[st] * cells / (vsec / args.variant_steps) / 1e9
+        variants[st] = {"value": round(cells * args.variant_steps / vsec / 1e6, 1),
+                        "unit": "MLUPS", "steps": args.variant_steps,
+                        "ms_per_step": round(vms / args.variant_steps, 5),
+                        "achieved_GBs": round(v_ach, 1),
+                        "frac": round(v_ach / HBM_PEAK_GBS, 4),
+                        "mass_drift_rel": float(abs(vdiag[0] - diag[0]) / diag[0])}
+
+    line = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.storage == "f64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"D2Q9 periodic {n}x{n} OReg sweep, rotated shear wave u0=0.05 "
+                               f"along atan(1/2), guided equilibrium, theta=1/3, tau={tau}, "
+                               f"{args.storage} storage, one lattice per launch",
+                   "nx": n, "ny": n, "tau": tau, "storage": args.storage},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "sweep_kernel",
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "variants": variants,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(n, tau, args.cpu_steps, fields)
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,185 @@
+/*
+ * oreg.h -- C ABI of the MI355X (gfx950) Onsager-regularized lattice
+ * Boltzmann library (liboreg.so).
+ *
+ * The library advances periodic D2Q9 lattices with the OReg method of
+ * Jonnalagadda, Agrawal, Sharma, Rocchia and Succi (arXiv 2501.16000):
+ * every time step applies, to every node x independently,
+ *
+ *   rho = <f, 1>, rho u = <f, c>                              (Eq. 2a)
+ *   f^eq(rho, u): guided equilibrium                          (Eq. 11)
+ *                 or second-order polynomial equilibrium      (Sec. III.D)
+ *   f^neq = f - f^eq;  f^OReg from f^neq                      (Eq. 6)
+ *   f_i(x + c_i, t + 1) = f_i^eq + (1 - 1/tau) f_i^OReg       (Eq. 7)
+ *
+ * with Delta t = 1.  The lattice-BGK update of Eq. (1) is available as a
+ * comparison scheme, and full-way bounce-back wall columns (Sec. IV,
+ * shocktube) as a boundary option.
+ *
+ * Conventions shared by every entry point:
+ *   - velocity order i = 0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1)
+ *                        5:(1,1) 6:(-1,1) 7:(-1,-1) 8:(1,-1);
+ *   - node (x, y), 0 <= x < nx, 0 <= y < ny, stored x fastest;
+ *   - fields are double [ny][nx]; populations are double [9][ny][nx];
+ *   - the observable state is the pre-collision f(x, t) of Eq. (7), with
+ *     t counted from the last lb_init / lb_set_populations.
+ *
+ * Ownership: a lattice owns its device memory for its whole life.  Host
+ * arrays passed in or out are owned by the caller, copied and never kept.
+ * Device pointers (the *_device calls) are owned by the caller, must be HIP
+ * device allocations on the lattice's device, and must stay valid until the
+ * work enqueued on the lattice's stream has completed (lb_sync).
+ *
+ * Errors: every call returns an lb_status; nothing throws or aborts across
+ * the ABI.  lb_last_error() gives a message for the last failing call on a
+ * lattice (or, for NULL, on the calling thread).
+ *
+ * Threading: calls on one lattice must not overlap (one lattice per thread,
+ * or external locking); distinct lattices are independent.
+ */
+#ifndef OREG_H
+#define OREG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lb_lattice lb_lattice;
+
+/* Equilibrium of the collision: Eq. (11) (any 0 < theta < 1) or the
+   second-order polynomial form of Sec. III.D at theta0 = 1/3. */
+typedef enum lb_equilibrium { LB_EQ_GUIDED = 0, LB_EQ_POLY2 = 1 } lb_equilibrium;
+
+/* Population storage in device memory.  LB_F64 keeps f_i in FP64 and
+   computes in FP64.  The shifted formats keep f_i - w_i rho0 (w_i the rest
+   equilibrium weights of the chosen equilibrium, rho0 the reference density
+   of lb_options) rounded to nearest-even in FP32, FP16 or BF16, and collide
+   in FP32 registers. */
+typedef enum lb_storage {
+  LB_F64 = 0,
+  LB_F32S = 1,
+  LB_F16S = 2,
+  LB_BF16S = 3
+} lb_storage;
+
+/* Collision: OReg (Eqs. 6, 7) or lattice BGK (Eq. 1). */
+typedef enum lb_collision { LB_COLL_OREG = 0, LB_COLL_BGK = 1 } lb_collision;
+
+/* Boundary in x: periodic, or full-way bounce-back wall nodes in columns
+   x = 0 and x = nx - 1 (they reverse every population instead of colliding;
+   the wall sits half-way to the first fluid column).  y is always periodic. */
+typedef enum lb_boundary { LB_BC_PERIODIC = 0, LB_BC_BOUNCEBACK = 1 } lb_boundary;
+
+typedef enum lb_status {
+  LB_OK = 0,
+  LB_EINVAL = -1,      /* invalid argument (see each call)                    */
+  LB_ENOMEM = -2,      /* a device allocation failed                          */
+  LB_EDEVICE = -3,     /* any other HIP error, or no usable device            */
+  LB_ESTATE = -4,      /* call not valid in the lattice's state (not inited)  */
+  LB_ENONFINITE = -5   /* lb_step with check_nonfinite found NaN/Inf          */
+} lb_status;
+
+typedef struct lb_options {
+  int nx, ny;                 /* lattice size, both >= 1                        */
+  double tau;                 /* relaxation time, > 1/2 (nu = theta (tau - 1/2)) */
+  double theta;               /* reduced temperature; 1/3 for LB_EQ_POLY2       */
+  lb_equilibrium equilibrium;
+  lb_storage storage;
+  lb_collision collision;
+  lb_boundary boundary_x;
+  double rho0;                /* reference density of shifted storage, > 0     */
+  void* stream;               /* hipStream_t to enqueue on; NULL: own stream    */
+  int device;                 /* HIP device ordinal; -1: current device         */
+  int check_nonfinite;        /* nonzero: lb_step scans for NaN/Inf afterwards  */
+} lb_options;
+
+/* Defaults: 0 x 0, tau 1, theta 1/3, guided, LB_F64, OReg, periodic, rho0 1,
+   own stream, current device, no checks.  NULL-safe. */
+void lb_options_init(lb_options* opt);
+
+/* FP64 periodic OReg lattice on the current device with its own stream.
+   LB_EINVAL: nx or ny < 1, too large, tau or theta not finite, tau <= 1/2,
+   guided with theta outside (0, 1), polynomial with |theta - 1/3| > 1e-12,
+   unknown enum, out == NULL.  LB_ENOMEM / LB_EDEVICE from HIP. */
+lb_status lb_create(int nx, int ny, double tau, double theta, lb_equilibrium eq,
+                    lb_lattice** out);
+
+/* Same as lb_create with every option; additionally LB_EINVAL for rho0 not
+   finite or <= 0 with shifted storage, or a device ordinal out of range. */
+lb_status lb_create_ex(const lb_options* opt, lb_lattice** out);
+
+/* f(x, 0) = f^eq(rho(x), u(x)) and t = 0.  rho, ux, uy: host double [ny][nx].
+   LB_EINVAL for a NULL pointer, a non-finite value or rho <= 0.  Synchronous. */
+lb_status lb_init(lb_lattice* h, const double* rho, const double* ux, const double* uy);
+
+/* lb_init from device arrays (e.g. torch tensors).  Enqueued on the
+   lattice's stream; waits for it to validate the fields (LB_EINVAL as in
+   lb_init, in which case the state is left uninitialized). */
+lb_status lb_init_device(lb_lattice* h, const double* rho, const double* ux,
+                         const double* uy);
+
+/* Enqueue n time steps on the lattice's stream and return (asynchronous).
+   n == 0 is a no-op.  LB_EINVAL for n < 0, LB_ESTATE before init.  With
+   check_nonfinite set, waits and returns LB_ENONFINITE if a node holds a
+   non-finite population. */
+lb_status lb_step(lb_lattice* h, int64_t n);
+
+/* rho, ux, uy of the pre-collision f(x, t): host double out[3][ny][nx].
+   Waits for the stream. */
+lb_status lb_moments(lb_lattice* h, double* out);
+
+/* Same into a device array out_dev[3][ny][nx]; enqueued, asynchronous. */
+lb_status lb_moments_device(lb_lattice* h, double* out_dev);
+
+/* Pre-collision populations f(x, t), unshifted, FP64: host double
+   out[9][ny][nx].  Waits for the stream. */
+lb_status lb_populations(lb_lattice* h, double* out);
+
+/* Replace the state by host populations in[9][ny][nx] (pre-collision, FP64,
+   unshifted; shifted storage rounds them) and set t = 0.  LB_EINVAL for a
+   non-finite value or a node with sum_i f_i <= 0.  Synchronous. */
+lb_status lb_set_populations(lb_lattice* h, const double* in);
+
+/* FP64 sums over all nodes of the pre-collision state, in a fixed reduction
+   order (bit-reproducible for a given lattice size):
+   out[0] mass sum rho, out[1..2] momentum sum rho u, out[3] kinetic energy
+   sum rho |u|^2 / 2, out[4] total energy sum (rho theta + rho |u|^2 / 2)
+   (E of Eq. 2a with p = rho theta, D = 2), out[5] number of nodes holding a
+   non-finite population (those nodes are left out of out[0..4]).
+   Waits for the stream. */
+lb_status lb_diagnostics(lb_lattice* h, double out[6]);
+
+/* y-average of rho(x) of the pre-collision state: host double out[nx].
+   Waits for the stream. */
+lb_status lb_density_profile(lb_lattice* h, double* out);
+
+/* Wait for all work enqueued on the lattice's stream. */
+lb_status lb_sync(lb_lattice* h);
+
+/* Time steps taken since the last init (-1 for NULL). */
+int64_t lb_time(const lb_lattice* h);
+
+/* Options the lattice was created with (NULL-safe: LB_EINVAL). */
+lb_status lb_get_options(const lb_lattice* h, lb_options* out);
+
+/* Bytes of device memory held by the lattice. */
+int64_t lb_device_bytes(const lb_lattice* h);
+
+/* Free the lattice and its device memory after its stream drains.
+   NULL-safe (returns LB_OK). */
+lb_status lb_destroy(lb_lattice* h);
+
+/* Static text for a status code. */
+const char* lb_status_string(lb_status s);
+
+/* Message of the last failing call on h, or of the calling thread's last
+   failing call when h is NULL; "" if none.  Valid until the next call. */
+const char* lb_last_error(const lb_lattice* h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OREG_H */

@@ -1,0 +1,214 @@
+// d2q9.hpp -- device-side D2Q9 lattice, storage codecs and the OReg collision.
+//
+// One node's collision in registers, written for gfx950 VALU arithmetic:
+//   moments rho, j (Eq. 2a); equilibrium factors of Eq. (11) or the
+//   polynomial equilibrium of Sec. III.D; the trace-free non-equilibrium
+//   stress S of Eq. (6) from second moments; f^OReg and the update of Eq. (7)
+//   (or Eq. (1) for lattice BGK).
+//
+// Algebraic forms used here instead of the printed ones (identical in exact
+// arithmetic):
+//   * the guided equilibrium factorizes into per-axis factors
+//     Psi(0, u) = 1 - theta - u^2 and Psi(+-1, u) = (theta +- u + u^2)/2,
+//     f^eq_i = rho Psi(c_ix, u_x) Psi(c_iy, u_y);
+//   * both equilibria reproduce Pi^eq = rho theta delta + rho u u exactly, so
+//     the trace-free stress of f^neq is taken from second moments of f:
+//       S_xx = -S_yy = s = ((f1 + f3) - (f2 + f4) - rho (ux^2 - uy^2)) / 2,
+//       S_xy = (f5 + f7) - (f6 + f8) - rho ux uy;
+//   * with a trace-free S, (C C - C^2/2 I):S = s (Cx^2 - Cy^2) + 2 S_xy Cx Cy,
+//     C = c_i - u, and f^post_i = f^eq_i (1 + kappa b_i) with
+//     kappa = (1 - 1/tau) / (2 rho theta^2).
+//   * shifted storage carries df_i = f_i - w_i rho0; the axis and diagonal
+//     weights are equal in pairs, so s and S_xy need no shift, and
+//     f^eq_i - w_i rho0 is formed from small differences to keep FP32
+//     cancellation out of the update.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "oreg.h"
+
+namespace oreg {
+
+// Velocity components in the order of the public header, and the index of
+// the opposite velocity (c_opp = -c_i).
+__host__ __device__ constexpr int cx_of(int i) {
+  return (i == 1 || i == 5 || i == 8) ? 1 : (i == 3 || i == 6 || i == 7) ? -1 : 0;
+}
+__host__ __device__ constexpr int cy_of(int i) {
+  return (i == 2 || i == 5 || i == 6) ? 1 : (i == 4 || i == 7 || i == 8) ? -1 : 0;
+}
+__host__ __device__ constexpr int opp_of(int i) {
+  return (i == 0) ? 0 : (i <= 4) ? ((i + 1) % 4 + 1) : ((i - 5 + 2) % 4 + 5);
+}
+static_assert(opp_of(1) == 3 && opp_of(2) == 4 && opp_of(3) == 1 && opp_of(4) == 2, "axis");
+static_assert(opp_of(5) == 7 && opp_of(6) == 8 && opp_of(7) == 5 && opp_of(8) == 6, "diag");
+
+// Compile-time loop over the nine populations.
+template <int I, int N, class F>
+__host__ __device__ __forceinline__ void unroll(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    unroll<I + 1, N>(f);
+  }
+}
+
+// ---------------------------------------------------------------- storage --
+template <int S> struct Storage;
+template <> struct Storage<LB_F64> {
+  using T = double;
+  using R = double;
+  static constexpr bool shifted = false;
+  __host__ __device__ static R load(T v) { return v; }
+  __host__ __device__ static T store(R v) { return v; }
+};
+template <> struct Storage<LB_F32S> {
+  using T = float;
+  using R = float;
+  static constexpr bool shifted = true;
+  __host__ __device__ static R load(T v) { return v; }
+  __host__ __device__ static T store(R v) { return v; }
+};
+template <> struct Storage<LB_F16S> {
+  using T = _Float16;
+  using R = float;
+  static constexpr bool shifted = true;
+  __host__ __device__ static R load(T v) { return (float)v; }
+  __host__ __device__ static T store(R v) { return (_Float16)v; }  // round to nearest even
+};
+template <> struct Storage<LB_BF16S> {
+  using T = __bf16;
+  using R = float;
+  static constexpr bool shifted = true;
+  __host__ __device__ static R load(T v) { return (float)v; }
+  __host__ __device__ static T store(R v) { return (__bf16)v; }  // v_cvt_pk_bf16_f32, RNE
+};
+
+// Per-lattice constants of the collision, precomputed on the host in FP64.
+struct Coef64 {
+  double theta;   // theta (exactly 1/3 for the polynomial equilibrium)
+  double a0, a1;  // rest per-axis factors 1 - theta and theta/2 (w_i = a_cx a_cy)
+  double kappa0;  // (1 - 1/tau) / (2 theta^2)
+  double omega;   // 1 / tau (lattice BGK)
+  double rho0;    // reference density of shifted storage (0 when unshifted)
+};
+
+// The same constants in the register type R.
+template <typename R>
+struct Coeffs {
+  R theta, a0, a1, kappa0, omega, rho0;
+  __host__ __device__ explicit Coeffs(const Coef64& c)
+      : theta((R)c.theta), a0((R)c.a0), a1((R)c.a1), kappa0((R)c.kappa0),
+        omega((R)c.omega), rho0((R)c.rho0) {}
+};
+
+// Per-axis factor selected by the velocity component c (-1, 0, +1).
+template <int c, typename R>
+__host__ __device__ __forceinline__ R pick(R m, R z, R p) {
+  if constexpr (c == 0) return z;
+  else if constexpr (c == 1) return p;
+  else return m;
+}
+
+// Peculiar velocity component C = c - u, formed without multiplying by c.
+template <int c, typename R>
+__host__ __device__ __forceinline__ R peculiar(R u) {
+  if constexpr (c == 0) return -u;
+  else if constexpr (c == 1) return R(1) - u;
+  else return R(-1) - u;
+}
+
+// Equilibrium of one node: feq_i (full value) and deq_i = feq_i - w_i rho0
+// (deq = feq when unshifted).  drho = rho - rho0 (= rho when unshifted).
+template <int EQ, bool SHIFTED, typename R>
+__host__ __device__ __forceinline__ void equilibrium(R drho, R rho, R ux, R uy, const Coeffs<R>& k,
+                                            R (&feq)[9], R (&deq)[9]) {
+  const R uxx = ux * ux, uyy = uy * uy;
+  if constexpr (EQ == LB_EQ_GUIDED) {
+    // Per-axis factors of Eq. (11) as rest value + small difference.
+    const R hx = R(0.5) * uxx, hy = R(0.5) * uyy;
+    const R dXm = hx - R(0.5) * ux, dX0 = -uxx, dXp = hx + R(0.5) * ux;
+    const R dYm = hy - R(0.5) * uy, dY0 = -uyy, dYp = hy + R(0.5) * uy;
+    const R Xm = k.a1 + dXm, X0 = k.a0 + dX0, Xp = k.a1 + dXp;
+    const R Ym = k.a1 + dYm, Y0 = k.a0 + dY0, Yp = k.a1 + dYp;
+    unroll<0, 9>([&](auto I) {
+      constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
+      const R X = pick<cx>(Xm, X0, Xp), Y = pick<cy>(Ym, Y0, Yp);
+      const R XY = X * Y;
+      feq[I.value] = rho * XY;
+      if constexpr (SHIFTED) {
+        const R dX = pick<cx>(dXm, dX0, dXp), dY = pick<cy>(dYm, dY0, dYp);
+        const R ax = (cx == 0) ? k.a0 : k.a1;
+        // rho X Y - rho0 ax ay = drho X Y + rho0 (dX Y + ax dY)
+        deq[I.value] = drho * XY + k.rho0 * (dX * Y + ax * dY);
+      } else {
+        deq[I.value] = feq[I.value];
+      }
+    });
+  } else {
+    // Polynomial equilibrium at theta0 = 1/3: rho W_i (1 + P_i),
+    // P_i = 3 c.u + 9/2 (c.u)^2 - 3/2 u^2.
+    const R u2h = R(1.5) * (uxx + uyy);
+    unroll<0, 9>([&](auto I) {
+      constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
+      R cu;
+      if constexpr (cx == 0 && cy == 0) cu = R(0);
+      else if constexpr (cx == 0) cu = (cy > 0) ? uy : -uy;
+      else if constexpr (cy == 0) cu = (cx > 0) ? ux : -ux;
+      else cu = ((cx > 0) ? ux : -ux) + ((cy > 0) ? uy : -uy);
+      const R W = ((cx == 0) ? k.a0 : k.a1) * ((cy == 0) ? k.a0 : k.a1);
+      R P;
+      if constexpr (cx == 0 && cy == 0) P = -u2h;
+      else P = cu * (R(3) + R(4.5) * cu) - u2h;
+      const R rW = rho * W;
+      feq[I.value] = rW + rW * P;
+      if constexpr (SHIFTED) deq[I.value] = drho * W + rW * P;
+      else deq[I.value] = feq[I.value];
+    });
+  }
+}
+
+// Collide one node in place.  f holds the pre-collision populations (shifted
+// by w_i rho0 when SHIFTED) and receives the post-collision ones (same shift).
+template <int EQ, int COLL, bool SHIFTED, typename R>
+__host__ __device__ __forceinline__ void collide(R (&f)[9], const Coeffs<R>& k) {
+  // Eq. (2a).  Sum w_i = 1 and sum w_i c_i = 0, so the shift only enters rho.
+  const R drho = f[0] + ((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8]));
+  const R jx = (f[1] - f[3]) + (f[5] - f[7]) + (f[8] - f[6]);
+  const R jy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
+  const R rho = SHIFTED ? k.rho0 + drho : drho;
+  const R inv = R(1) / rho;
+  const R ux = jx * inv, uy = jy * inv;
+
+  R feq[9], deq[9];
+  equilibrium<EQ, SHIFTED>(drho, rho, ux, uy, k, feq, deq);
+
+  if constexpr (COLL == LB_COLL_BGK) {
+    // Eq. (1): f + (f^eq - f) / tau (the shift cancels in the difference).
+    unroll<0, 9>([&](auto I) { f[I.value] = f[I.value] + k.omega * (deq[I.value] - f[I.value]); });
+    return;
+  } else {
+    // Trace-free non-equilibrium stress of Eq. (6) from second moments.
+    const R s = R(0.5) * (((f[1] + f[3]) - (f[2] + f[4])) - rho * (ux * ux - uy * uy));
+    const R sxy = ((f[5] + f[7]) - (f[6] + f[8])) - rho * (ux * uy);
+    const R two_sxy = sxy + sxy;
+    const R kappa = k.kappa0 * inv;
+    // Eqs. (6), (7): f^post_i = f^eq_i + kappa f^eq_i b_i.
+    unroll<0, 9>([&](auto I) {
+      constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
+      const R Cx = peculiar<cx>(ux), Cy = peculiar<cy>(uy);
+      const R b = s * (Cx * Cx - Cy * Cy) + two_sxy * (Cx * Cy);
+      f[I.value] = deq[I.value] + (kappa * feq[I.value]) * b;
+    });
+  }
+}
+
+// Rest weight times rho0 of a population with velocity (cx, cy), in FP64.
+__host__ __device__ __forceinline__ double shift64(int cx, int cy, const Coef64& c) {
+  return ((cx == 0) ? c.a0 : c.a1) * ((cy == 0) ? c.a0 : c.a1) * c.rho0;
+}
+
+}  // namespace oreg

@@ -1,0 +1,392 @@
+// kernels.hip -- D2Q9 OReg kernels for gfx950 and their launchers.
+//
+// The sweep is one fused pass per time step: pull the nine populations of a
+// node from their upwind neighbours (periodic wrap), collide in registers
+// (d2q9.hpp), store the node's nine post-collision populations.  Every plane
+// element of the source is read by exactly one node, so the pass moves
+// 2 * 9 * sizeof(storage) bytes per node and is bound by HBM bandwidth.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "kernels.hpp"
+
+namespace oreg {
+namespace {
+
+constexpr int kThreads = 256;
+
+template <int V>
+using IC = std::integral_constant<int, V>;
+
+// ------------------------------------------------------------- dispatch --
+template <class F>
+hipError_t with_storage(int st, F&& f) {
+  switch (st) {
+    case LB_F64: return f(IC<LB_F64>{});
+    case LB_F32S: return f(IC<LB_F32S>{});
+    case LB_F16S: return f(IC<LB_F16S>{});
+    case LB_BF16S: return f(IC<LB_BF16S>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+template <class F>
+hipError_t with_eq(int eq, F&& f) {
+  switch (eq) {
+    case LB_EQ_GUIDED: return f(IC<LB_EQ_GUIDED>{});
+    case LB_EQ_POLY2: return f(IC<LB_EQ_POLY2>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+template <class F>
+hipError_t with_coll(int coll, F&& f) {
+  switch (coll) {
+    case LB_COLL_OREG: return f(IC<LB_COLL_OREG>{});
+    case LB_COLL_BGK: return f(IC<LB_COLL_BGK>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+template <class F>
+hipError_t with_bc(int bc, F&& f) {
+  switch (bc) {
+    case LB_BC_PERIODIC: return f(IC<LB_BC_PERIODIC>{});
+    case LB_BC_BOUNCEBACK: return f(IC<LB_BC_BOUNCEBACK>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+__device__ __forceinline__ int wrap_dec(int v, int n) { return v == 0 ? n - 1 : v - 1; }
+__device__ __forceinline__ int wrap_inc(int v, int n) { return v == n - 1 ? 0 : v + 1; }
+__device__ __forceinline__ int wrap_sub(int v, int c, int n) {
+  return c == 0 ? v : (c > 0 ? wrap_dec(v, n) : wrap_inc(v, n));
+}
+
+// ---------------------------------------------------------------- sweep --
+template <int EQ, int COLL, int BC, int ST>
+__global__ __launch_bounds__(kThreads) void sweep_kernel(
+    const typename Storage<ST>::T* __restrict__ src, typename Storage<ST>::T* __restrict__ dst,
+    Geometry g, Coef64 c, int nseg) {
+  using S = Storage<ST>;
+  using R = typename S::R;
+  const int y = blockIdx.x / nseg;
+  const int x = (blockIdx.x - y * nseg) * kThreads + threadIdx.x;
+  if (x >= g.nx) return;
+  const int nx = g.nx, ny = g.ny;
+  const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
+  const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
+  const int64_t P = g.plane;
+  const int64_t r0 = (int64_t)y * nx, rm = (int64_t)ym * nx, rp = (int64_t)yp * nx;
+  // Pull f_i(x) = g_i(x - c_i).
+  R f[9];
+  f[0] = S::load(src[0 * P + r0 + x]);
+  f[1] = S::load(src[1 * P + r0 + xm]);
+  f[2] = S::load(src[2 * P + rm + x]);
+  f[3] = S::load(src[3 * P + r0 + xp]);
+  f[4] = S::load(src[4 * P + rp + x]);
+  f[5] = S::load(src[5 * P + rm + xm]);
+  f[6] = S::load(src[6 * P + rm + xp]);
+  f[7] = S::load(src[7 * P + rp + xp]);
+  f[8] = S::load(src[8 * P + rp + xm]);
+  if (BC == LB_BC_BOUNCEBACK && (x == 0 || x == nx - 1)) {
+    // Full-way bounce-back wall node: reverse every population.
+    R r[9];
+    unroll<0, 9>([&](auto I) { r[I.value] = f[opp_of(I.value)]; });
+    unroll<0, 9>([&](auto I) { dst[I.value * P + r0 + x] = S::store(r[I.value]); });
+    return;
+  }
+  collide<EQ, COLL, S::shifted>(f, Coeffs<R>(c));
+  unroll<0, 9>([&](auto I) { dst[I.value * P + r0 + x] = S::store(f[I.value]); });
+}
+
+// ----------------------------------------------------------------- init --
+template <int EQ, int ST>
+__global__ __launch_bounds__(kThreads) void init_kernel(const double* __restrict__ rho,
+                                                        const double* __restrict__ ux,
+                                                        const double* __restrict__ uy,
+                                                        typename Storage<ST>::T* __restrict__ dst,
+                                                        Geometry g, Coef64 c,
+                                                        unsigned int* __restrict__ bad) {
+  using S = Storage<ST>;
+  using R = typename S::R;
+  const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= g.plane) return;
+  const int y = (int)(idx / g.nx);
+  const int x = (int)(idx - (int64_t)y * g.nx);
+  double r = rho[idx], vx = ux[idx], vy = uy[idx];
+  if (!(isfinite(r) && isfinite(vx) && isfinite(vy) && r > 0.0)) {
+    atomicAdd(bad, 1u);
+    r = 1.0;
+    vx = vy = 0.0;
+  }
+  const Coeffs<double> k(c);
+  double feq[9], deq[9];
+  equilibrium<EQ, S::shifted>(S::shifted ? r - c.rho0 : r, r, vx, vy, k, feq, deq);
+  // f_i(x, 0) = f^eq_i(x) is stored as g_i(x - c_i).
+  unroll<0, 9>([&](auto I) {
+    constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
+    const int xd = wrap_sub(x, cx, g.nx), yd = wrap_sub(y, cy, g.ny);
+    dst[I.value * g.plane + (int64_t)yd * g.nx + xd] = S::store((R)deq[I.value]);
+  });
+}
+
+// ------------------------------------------------------- import / export --
+template <int ST>
+__global__ __launch_bounds__(kThreads) void import_kernel(int i, const double* __restrict__ fin,
+                                                          typename Storage<ST>::T* __restrict__ dst,
+                                                          Geometry g, Coef64 c) {
+  using S = Storage<ST>;
+  using R = typename S::R;
+  const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= g.plane) return;
+  const int y = (int)(idx / g.nx);
+  const int x = (int)(idx - (int64_t)y * g.nx);
+  const int cx = cx_of(i), cy = cy_of(i);
+  const double w = S::shifted ? shift64(cx, cy, c) : 0.0;
+  const int xd = wrap_sub(x, cx, g.nx), yd = wrap_sub(y, cy, g.ny);
+  dst[i * g.plane + (int64_t)yd * g.nx + xd] = S::store((R)(fin[idx] - w));
+}
+
+template <int ST>
+__global__ __launch_bounds__(kThreads) void export_kernel(int i,
+                                                          const typename Storage<ST>::T* __restrict__ src,
+                                                          double* __restrict__ fout, Geometry g,
+                                                          Coef64 c) {
+  using S = Storage<ST>;
+  const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= g.plane) return;
+  const int y = (int)(idx / g.nx);
+  const int x = (int)(idx - (int64_t)y * g.nx);
+  const int cx = cx_of(i), cy = cy_of(i);
+  const double w = S::shifted ? shift64(cx, cy, c) : 0.0;
+  const int xs = wrap_sub(x, cx, g.nx), ys = wrap_sub(y, cy, g.ny);
+  fout[idx] = (double)S::load(src[i * g.plane + (int64_t)ys * g.nx + xs]) + w;
+}
+
+// Pre-collision populations of node (x, y) in FP64, still shifted by w_i rho0.
+template <int ST>
+__device__ __forceinline__ void gather64(const typename Storage<ST>::T* __restrict__ src,
+                                         const Geometry& g, int x, int y, double (&d)[9]) {
+  using S = Storage<ST>;
+  const int xm = wrap_dec(x, g.nx), xp = wrap_inc(x, g.nx);
+  const int ym = wrap_dec(y, g.ny), yp = wrap_inc(y, g.ny);
+  const int64_t P = g.plane;
+  const int64_t r0 = (int64_t)y * g.nx, rm = (int64_t)ym * g.nx, rp = (int64_t)yp * g.nx;
+  d[0] = (double)S::load(src[0 * P + r0 + x]);
+  d[1] = (double)S::load(src[1 * P + r0 + xm]);
+  d[2] = (double)S::load(src[2 * P + rm + x]);
+  d[3] = (double)S::load(src[3 * P + r0 + xp]);
+  d[4] = (double)S::load(src[4 * P + rp + x]);
+  d[5] = (double)S::load(src[5 * P + rm + xm]);
+  d[6] = (double)S::load(src[6 * P + rm + xp]);
+  d[7] = (double)S::load(src[7 * P + rp + xp]);
+  d[8] = (double)S::load(src[8 * P + rp + xm]);
+}
+
+// rho - rho0 and j of shifted populations (sum w_i = 1, sum w_i c_i = 0).
+__device__ __forceinline__ void moments64(const double (&d)[9], double& drho, double& jx,
+                                          double& jy) {
+  drho = d[0] + ((d[1] + d[3]) + (d[2] + d[4])) + ((d[5] + d[7]) + (d[6] + d[8]));
+  jx = (d[1] - d[3]) + (d[5] - d[7]) + (d[8] - d[6]);
+  jy = (d[2] - d[4]) + (d[5] - d[7]) + (d[6] - d[8]);
+}
+
+template <int ST>
+__global__ __launch_bounds__(kThreads) void moments_kernel(const typename Storage<ST>::T* __restrict__ src,
+                                                           double* __restrict__ out, Geometry g,
+                                                           Coef64 c) {
+  const int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (idx >= g.plane) return;
+  const int y = (int)(idx / g.nx);
+  const int x = (int)(idx - (int64_t)y * g.nx);
+  double d[9], drho, jx, jy;
+  gather64<ST>(src, g, x, y, d);
+  moments64(d, drho, jx, jy);
+  const double rho = c.rho0 + drho;
+  out[idx] = rho;
+  out[g.plane + idx] = jx / rho;
+  out[2 * g.plane + idx] = jy / rho;
+}
+
+// ---------------------------------------------------------- diagnostics --
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// Fixed-order block sum of 6 values; result valid in thread 0.
+__device__ __forceinline__ void block_sum6(double (&v)[6]) {
+  __shared__ double part[kThreads / 64][6];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) part[wave][k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      double s = part[0][k];
+      for (int w = 1; w < kThreads / 64; ++w) s += part[w][k];
+      v[k] = s;
+    }
+  }
+}
+
+template <int ST>
+__global__ __launch_bounds__(kThreads) void diag_kernel(const typename Storage<ST>::T* __restrict__ src,
+                                                        double* __restrict__ partials, Geometry g,
+                                                        Coef64 c, double theta) {
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  const int64_t stride = (int64_t)gridDim.x * kThreads;
+  for (int64_t idx = (int64_t)blockIdx.x * kThreads + threadIdx.x; idx < g.plane; idx += stride) {
+    const int y = (int)(idx / g.nx);
+    const int x = (int)(idx - (int64_t)y * g.nx);
+    double d[9], drho, jx, jy;
+    gather64<ST>(src, g, x, y, d);
+    bool finite = true;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) finite = finite && isfinite(d[i]);
+    if (!finite) {
+      acc[5] += 1.0;
+      continue;
+    }
+    moments64(d, drho, jx, jy);
+    const double rho = c.rho0 + drho;
+    const double ke = 0.5 * (jx * jx + jy * jy) / rho;
+    acc[0] += rho;
+    acc[1] += jx;
+    acc[2] += jy;
+    acc[3] += ke;
+    acc[4] += rho * theta + ke;
+  }
+  block_sum6(acc);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) partials[blockIdx.x * 6 + k] = acc[k];
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void diag_final_kernel(const double* __restrict__ partials,
+                                                              int nblocks, double* __restrict__ out) {
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int b = threadIdx.x; b < nblocks; b += kThreads) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) acc[k] += partials[b * 6 + k];
+  }
+  block_sum6(acc);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) out[k] = acc[k];
+  }
+}
+
+template <int ST>
+__global__ __launch_bounds__(kThreads) void profile_kernel(const typename Storage<ST>::T* __restrict__ src,
+                                                           double* __restrict__ out, Geometry g,
+                                                           Coef64 c) {
+  const int x = blockIdx.x * kThreads + threadIdx.x;
+  if (x >= g.nx) return;
+  double sum = 0.0;
+  for (int y = 0; y < g.ny; ++y) {
+    double d[9], drho, jx, jy;
+    gather64<ST>(src, g, x, y, d);
+    moments64(d, drho, jx, jy);
+    sum += c.rho0 + drho;
+  }
+  out[x] = sum / g.ny;
+}
+
+unsigned int blocks_for(int64_t n) { return (unsigned int)((n + kThreads - 1) / kThreads); }
+
+}  // namespace
+
+// ------------------------------------------------------------ launchers --
+hipError_t launch_sweep(int eq, int coll, int bc, int st, const void* src, void* dst,
+                        const Geometry& g, const Coef64& c, hipStream_t s) {
+  const int nseg = (g.nx + kThreads - 1) / kThreads;
+  const unsigned int nblocks = (unsigned int)nseg * (unsigned int)g.ny;
+  return with_storage(st, [&](auto ST) {
+    using T = typename Storage<ST.value>::T;
+    return with_eq(eq, [&](auto EQ) {
+      return with_coll(coll, [&](auto CO) {
+        return with_bc(bc, [&](auto BC) {
+          sweep_kernel<EQ.value, CO.value, BC.value, ST.value><<<nblocks, kThreads, 0, s>>>(
+              static_cast<const T*>(src), static_cast<T*>(dst), g, c, nseg);
+          return hipGetLastError();
+        });
+      });
+    });
+  });
+}
+
+hipError_t launch_init(int eq, int st, const double* rho, const double* ux, const double* uy,
+                       void* dst, const Geometry& g, const Coef64& c, unsigned int* bad,
+                       hipStream_t s) {
+  return with_storage(st, [&](auto ST) {
+    using T = typename Storage<ST.value>::T;
+    return with_eq(eq, [&](auto EQ) {
+      init_kernel<EQ.value, ST.value><<<blocks_for(g.plane), kThreads, 0, s>>>(
+          rho, ux, uy, static_cast<T*>(dst), g, c, bad);
+      return hipGetLastError();
+    });
+  });
+}
+
+hipError_t launch_import_plane(int st, int i, const double* fin, void* dst, const Geometry& g,
+                               const Coef64& c, hipStream_t s) {
+  return with_storage(st, [&](auto ST) {
+    using T = typename Storage<ST.value>::T;
+    import_kernel<ST.value><<<blocks_for(g.plane), kThreads, 0, s>>>(i, fin, static_cast<T*>(dst),
+                                                                      g, c);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_export_plane(int st, int i, const void* src, double* fout, const Geometry& g,
+                               const Coef64& c, hipStream_t s) {
+  return with_storage(st, [&](auto ST) {
+    using T = typename Storage<ST.value>::T;
+    export_kernel<ST.value><<<blocks_for(g.plane), kThreads, 0, s>>>(
+        i, static_cast<const T*>(src), fout, g, c);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_moments(int st, const void* src, double* out, const Geometry& g,
+                          const Coef64& c, hipStream_t s) {
+  return with_storage(st, [&](auto ST) {
+    using T = typename Storage<ST.value>::T;
+    moments_kernel<ST.value><<<blocks_for(g.plane), kThreads, 0, s>>>(static_cast<const T*>(src),
+                                                                       out, g, c);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_diagnostics(int st, const void* src, double* partials, double* out,
+                              const Geometry& g, const Coef64& c, double theta_energy,
+                              hipStream_t s) {
+  return with_storage(st, [&](auto ST) {
+    using T = typename Storage<ST.value>::T;
+    diag_kernel<ST.value><<<kDiagBlocks, kThreads, 0, s>>>(static_cast<const T*>(src), partials, g,
+                                                           c, theta_energy);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    diag_final_kernel<<<1, kThreads, 0, s>>>(partials, kDiagBlocks, out);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_profile(int st, const void* src, double* out, const Geometry& g,
+                          const Coef64& c, hipStream_t s) {
+  return with_storage(st, [&](auto ST) {
+    using T = typename Storage<ST.value>::T;
+    profile_kernel<ST.value><<<blocks_for(g.nx), kThreads, 0, s>>>(static_cast<const T*>(src),
+                                                                    out, g, c);
+    return hipGetLastError();
+  });
+}
+
+}  // namespace oreg

@@ -1,0 +1,58 @@
+// kernels.hpp -- host-side launchers of the D2Q9 OReg kernels (gfx950).
+//
+// Internal storage convention of a lattice buffer: plane i holds the
+// post-collision, not yet streamed populations g_i, so that the observable
+// pre-collision state of Eq. (7) is f_i(x, t) = g_i(x - c_i) (periodic).
+// A sweep pulls g_i(x - c_i) from one buffer, collides, and stores g_i(x)
+// into the other; streaming is the pull.  Shifted storage keeps g_i - w_i rho0.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "d2q9.hpp"
+
+namespace oreg {
+
+struct Geometry {
+  int nx, ny;
+  int64_t plane;  // nx * ny
+};
+
+// Number of workgroups of the diagnostics reduction (fixed: the reduction
+// order, hence the FP64 result, depends only on the lattice size).
+constexpr int kDiagBlocks = 1024;
+
+// One time step: src -> dst.
+hipError_t launch_sweep(int eq, int coll, int bc, int st, const void* src, void* dst,
+                        const Geometry& g, const Coef64& c, hipStream_t s);
+
+// g from fields (device FP64 [ny][nx] each); counts invalid input nodes
+// (non-finite value or rho <= 0) into *bad.
+hipError_t launch_init(int eq, int st, const double* rho, const double* ux, const double* uy,
+                       void* dst, const Geometry& g, const Coef64& c, unsigned int* bad,
+                       hipStream_t s);
+
+// Plane i of g from plane i of pre-collision FP64 populations (device).
+hipError_t launch_import_plane(int st, int i, const double* fin, void* dst, const Geometry& g,
+                               const Coef64& c, hipStream_t s);
+
+// Plane i of the pre-collision FP64 populations (device) from g.
+hipError_t launch_export_plane(int st, int i, const void* src, double* fout, const Geometry& g,
+                               const Coef64& c, hipStream_t s);
+
+// rho, ux, uy of the pre-collision state into out[3][ny][nx] (device FP64).
+hipError_t launch_moments(int st, const void* src, double* out, const Geometry& g,
+                          const Coef64& c, hipStream_t s);
+
+// Diagnostics of the pre-collision state: partials[kDiagBlocks][6] scratch,
+// out[6] result (device FP64).
+hipError_t launch_diagnostics(int st, const void* src, double* partials, double* out,
+                              const Geometry& g, const Coef64& c, double theta_energy,
+                              hipStream_t s);
+
+// y-average of rho(x): out[nx] (device FP64).
+hipError_t launch_profile(int st, const void* src, double* out, const Geometry& g,
+                          const Coef64& c, hipStream_t s);
+
+}  // namespace oreg

@@ -1,0 +1,108 @@
+"""Host-side checks of the C ABI (no kernel launches): the library loads,
+exports every entry point that include/oreg.h declares, and validates its
+arguments before it touches a device."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "oreg.h")
+
+
+def oreg():
+    from paper_2501_16000_amd import oreg as m
+    return m
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("lb_create", "lb_init", "lb_step", "lb_moments"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    m = oreg()
+    out = subprocess.run(["nm", "-D", "--defined-only", m.LIBRARY_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (lb_[a-z_0-9]+)$", out, flags=re.M))
+    missing = [n for n in declared_functions() if n not in exported]
+    assert not missing, f"declared but not exported: {missing}"
+    assert sorted(m.EXPORTED) == declared_functions()
+
+
+def test_options_defaults_and_struct_layout():
+    m = oreg()
+    o = m.lb_options()
+    m.lb_options_init(ctypes.byref(o))
+    assert (o.nx, o.ny) == (0, 0)
+    assert o.tau == 1.0 and abs(o.theta - 1 / 3) < 1e-16
+    assert o.equilibrium == m.LB_EQ_GUIDED and o.storage == m.LB_F64
+    assert o.collision == m.LB_COLL_OREG and o.boundary_x == m.LB_BC_PERIODIC
+    assert o.rho0 == 1.0 and o.device == -1 and not o.stream and o.check_nonfinite == 0
+    # C layout of lb_options: 2 ints, 2 doubles, 4 enums, double, pointer, 2 ints
+    assert ctypes.sizeof(m.lb_options) == 4 * 2 + 8 * 2 + 4 * 4 + 8 + 8 + 4 * 2
+
+
+INVALID = [
+    dict(nx=0, ny=8), dict(nx=8, ny=-1), dict(tau=0.5), dict(tau=0.3), dict(tau=math.nan),
+    dict(tau=math.inf), dict(theta=0.0), dict(theta=1.0), dict(theta=math.nan),
+    dict(equilibrium=1, theta=0.35), dict(equilibrium=7), dict(storage=9), dict(collision=3),
+    dict(boundary_x=5), dict(storage=1, rho0=0.0), dict(storage=2, rho0=-1.0),
+    dict(storage=3, rho0=math.inf), dict(nx=1, ny=20_000_000),
+]
+
+
+@pytest.mark.parametrize("bad", INVALID)
+def test_create_rejects_invalid_options(bad):
+    m = oreg()
+    o = m.lb_options()
+    m.lb_options_init(ctypes.byref(o))
+    o.nx, o.ny, o.tau = 8, 8, 0.8
+    for k, v in bad.items():
+        setattr(o, k, v)
+    h = ctypes.c_void_p(123)
+    st = m.lb_create_ex(ctypes.byref(o), ctypes.byref(h))
+    assert st == m.LB_EINVAL
+    assert h.value is None
+    assert m.lb_last_error(None).decode()
+
+
+def test_null_arguments():
+    m = oreg()
+    assert m.lb_create(8, 8, 0.8, 1 / 3, 0, None) == m.LB_EINVAL
+    assert m.lb_create_ex(None, ctypes.byref(ctypes.c_void_p())) == m.LB_EINVAL
+    assert m.lb_step(None, 1) == m.LB_EINVAL
+    assert m.lb_init(None, None, None, None) == m.LB_EINVAL
+    assert m.lb_moments(None, None) == m.LB_EINVAL
+    assert m.lb_sync(None) == m.LB_EINVAL
+    assert m.lb_destroy(None) == m.LB_OK
+    assert m.lb_time(None) == -1
+    assert m.lb_device_bytes(None) == 0
+
+
+def test_status_strings():
+    m = oreg()
+    for code in (m.LB_OK, m.LB_EINVAL, m.LB_ENOMEM, m.LB_EDEVICE, m.LB_ESTATE, m.LB_ENONFINITE):
+        assert m.lb_status_string(code).decode().startswith("LB_")
+    assert m.lb_status_string(42) == b"unknown lb_status"
+
+
+def test_valid_create_without_device_reports_edevice():
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is visible; device creation is covered by the gpu tests")
+    m = oreg()
+    h = ctypes.c_void_p()
+    assert m.lb_create(8, 8, 0.8, 1 / 3, m.LB_EQ_GUIDED, ctypes.byref(h)) == m.LB_EDEVICE
+    assert h.value is None
+    assert "device" in m.lb_last_error(None).decode()

@@ -53,9 +53,10 @@ def parse():
 def time_lattice(oreg, torch, n, tau, storage, steps, warmup, fields):
     """Return (elapsed_ms, steps) of `steps` sweeps timed with HIP events on
     the stream the sweep is launched on."""
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream()  # default priority
     rho0 = 1.0
-    with oreg.Lattice(n, n, tau, 1.0 / 3.0, storage=storage, rho0=rho0, stream=stream) as lat:
+    with torch.cuda.stream(stream), \
+            oreg.Lattice(n, n, tau, 1.0 / 3.0, storage=storage, rho0=rho0, stream=stream) as lat:
         lat.init(*fields)
         lat.step(warmup)
         torch.cuda.synchronize()

@@ -90,13 +90,17 @@ typedef struct lb_options {
   lb_collision collision;
   lb_boundary boundary_x;
   double rho0;                /* reference density of shifted storage, > 0     */
-  void* stream;               /* hipStream_t to enqueue on; NULL: own stream    */
+  void* stream;               /* hipStream_t to enqueue on when use_stream      */
+  int use_stream;             /* 0: the lattice creates and owns a non-blocking
+                                 stream; 1: enqueue on `stream` (NULL = the
+                                 device's null stream), owned by the caller and
+                                 kept alive until lb_destroy returns           */
   int device;                 /* HIP device ordinal; -1: current device         */
   int check_nonfinite;        /* nonzero: lb_step scans for NaN/Inf afterwards  */
 } lb_options;
 
 /* Defaults: 0 x 0, tau 1, theta 1/3, guided, LB_F64, OReg, periodic, rho0 1,
-   own stream, current device, no checks.  NULL-safe. */
+   own stream (use_stream 0), current device, no checks.  NULL-safe. */
 void lb_options_init(lb_options* opt);
 
 /* FP64 periodic OReg lattice on the current device with its own stream.

@@ -20,7 +20,10 @@ SOURCES = ["lattice.hip", "kernels.hip", "serve.hip"]
 
 ARCH = "gfx950"
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
+# Code object v5 loads under every ROCm 6/7 runtime, including the one that a
+# PyTorch wheel may bring into the process.
 COMMON = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall",
+          "-mcode-object-version=5",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I", INCLUDE, "-I", CSRC]
 

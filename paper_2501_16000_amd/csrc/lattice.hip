@@ -166,6 +166,7 @@ void lb_options_init(lb_options* o) {
   o->boundary_x = LB_BC_PERIODIC;
   o->rho0 = 1.0;
   o->stream = nullptr;
+  o->use_stream = 0;
   o->device = -1;
   o->check_nonfinite = 0;
 }
@@ -220,7 +221,7 @@ lb_status lb_create_ex(const lb_options* opt, lb_lattice** out) {
     lb_destroy(h);
     return s;
   };
-  if (opt->stream) {
+  if (opt->use_stream) {
     h->stream = static_cast<hipStream_t>(opt->stream);
   } else {
     e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
@@ -431,7 +432,8 @@ lb_status lb_destroy(lb_lattice* h) {
   lb_status st = LB_OK;
   {
     DeviceScope ds(h->device);
-    if (h->stream && hipStreamSynchronize(h->stream) != hipSuccess) st = LB_EDEVICE;
+    if ((h->stream || !h->own_stream) && hipStreamSynchronize(h->stream) != hipSuccess)
+      st = LB_EDEVICE;
     for (int b = 0; b < 2; ++b)
       if (h->buf[b]) (void)hipFree(h->buf[b]);
     if (h->tmp) (void)hipFree(h->tmp);

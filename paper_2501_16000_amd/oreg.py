@@ -25,6 +25,14 @@ if not os.path.exists(LIBRARY_PATH):
         f"{LIBRARY_PATH} is missing: build it with `python -m paper_2501_16000_amd.build` "
         "(hipcc, gfx950)")
 
+# One process holds one HIP runtime.  libamdhip64 is resolved by soname, so the
+# first copy loaded serves every library; when PyTorch is installed, load it
+# first so that its tensors, streams and this library share its runtime.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 _lib = ctypes.CDLL(LIBRARY_PATH)
 
 # ----------------------------------------------------------------- enums --
@@ -49,6 +57,7 @@ class lb_options(ctypes.Structure):
         ("collision", ctypes.c_int), ("boundary_x", ctypes.c_int),
         ("rho0", ctypes.c_double),
         ("stream", ctypes.c_void_p),
+        ("use_stream", ctypes.c_int),
         ("device", ctypes.c_int),
         ("check_nonfinite", ctypes.c_int),
     ]
@@ -130,7 +139,8 @@ class Lattice:
     Parameters mirror ``lb_options``; string names select the enums:
     equilibrium 'guided' | 'poly2', storage 'f64' | 'f32s' | 'f16s' | 'bf16s',
     collision 'oreg' | 'bgk', boundary_x 'periodic' | 'bounceback'.
-    ``stream`` is a HIP stream handle (int) or a ``torch.cuda.Stream``.
+    ``stream`` is a HIP stream handle (int, 0 = the null stream) or a
+    ``torch.cuda.Stream``; None lets the lattice create its own stream.
     """
 
     def __init__(self, nx: int, ny: int, tau: float, theta: float = 1.0 / 3.0,
@@ -145,9 +155,11 @@ class Lattice:
         o.collision = COLLISIONS[collision]
         o.boundary_x = BOUNDARIES[boundary_x]
         o.rho0 = float(rho0)
-        if stream is not None and hasattr(stream, "cuda_stream"):
-            stream = stream.cuda_stream
-        o.stream = stream
+        if stream is not None:
+            if hasattr(stream, "cuda_stream"):
+                stream = stream.cuda_stream
+            o.stream = int(stream) or None
+            o.use_stream = 1
         o.device = int(device)
         o.check_nonfinite = int(bool(check_nonfinite))
         h = _H()

@@ -49,8 +49,9 @@ def test_options_defaults_and_struct_layout():
     assert o.equilibrium == m.LB_EQ_GUIDED and o.storage == m.LB_F64
     assert o.collision == m.LB_COLL_OREG and o.boundary_x == m.LB_BC_PERIODIC
     assert o.rho0 == 1.0 and o.device == -1 and not o.stream and o.check_nonfinite == 0
-    # C layout of lb_options: 2 ints, 2 doubles, 4 enums, double, pointer, 2 ints
-    assert ctypes.sizeof(m.lb_options) == 4 * 2 + 8 * 2 + 4 * 4 + 8 + 8 + 4 * 2
+    assert o.use_stream == 0
+    # C layout of lb_options: 2 ints, 2 doubles, 4 enums, double, pointer, 3 ints (+pad)
+    assert ctypes.sizeof(m.lb_options) == 4 * 2 + 8 * 2 + 4 * 4 + 8 + 8 + 4 * 3 + 4
 
 
 INVALID = [

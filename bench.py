@@ -45,8 +45,14 @@ def parse():
                    help="other storages to time on the same workload ('' for none)")
     p.add_argument("--variant-steps", type=int, default=300)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-steps", type=int, default=4,
+    p.add_argument("--cpu-steps", type=int, default=10,
                    help="oracle steps on the full lattice for the CPU baseline")
+    p.add_argument("--pmc-workload", action="store_true",
+                   help="only run a few sweeps per storage plus a 1 GiB device copy "
+                        "(the workload profiled with rocprofv3 --pmc)")
+    p.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                   help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of "
+                        "--pmc-workload into " + os.path.relpath(TRAFFIC_FILE, ROOT))
     return p.parse_args()
 
 
@@ -94,6 +100,70 @@ def kernel_source_sha():
     return h.hexdigest()[:16]
 
 
+COPY_BYTES = 1 << 30
+
+
+def pmc_workload(oreg, torch, n, tau, fields):
+    """A few sweeps per storage and one plain 1 GiB device-to-device copy, the
+    calibration of the HBM counters."""
+    for st in ("f64", "f32s", "bf16s"):
+        time_lattice(oreg, torch, n, tau, st, 5, 2, fields)
+    src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+
+
+def summarize_pmc(fetch_csv, write_csv, n):
+    """HBM bytes per sweep launch from FETCH_SIZE and WRITE_SIZE (KiB per
+    dispatch), each scaled by the ratio of known bytes to the counter's
+    reading for the plain copy."""
+    import csv
+    from collections import defaultdict
+
+    def read(path, counter):
+        """Mean counter value per kernel name, and the largest single dispatch
+        of the runtime's copy kernel (the 1 GiB calibration copy)."""
+        vals, copy = defaultdict(list), 0.0
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                v = float(row["Counter_Value"])
+                vals[row["Kernel_Name"]].append(v)
+                if "copyBuffer" in row["Kernel_Name"]:
+                    copy = max(copy, v)
+        return {k: sum(v) / len(v) for k, v in vals.items()}, copy
+
+    fetch, copy_f = read(fetch_csv, "FETCH_SIZE")
+    write, copy_w = read(write_csv, "WRITE_SIZE")
+    f_scale = COPY_BYTES / (copy_f * 1024.0)
+    w_scale = COPY_BYTES / (copy_w * 1024.0)
+    out = {"source": "rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE of "
+                     "`bench.py --pmc-workload`, scaled by a 1 GiB device copy",
+           "copy_fetch_scale": f_scale, "copy_write_scale": w_scale,
+           "kernel_source_sha": kernel_source_sha(), "kernels": {}}
+    sts = {"Storage<0>": "f64", "Storage<1>": "f32s", "Storage<2>": "f16s", "Storage<3>": "bf16s"}
+    for k, v in fetch.items():
+        if "sweep_kernel" not in k:
+            continue
+        st = next((name for tag, name in sts.items() if tag in k), None)
+        if st is None or k not in write:
+            continue
+        fb = v * 1024.0 * f_scale
+        wb = write[k] * 1024.0 * w_scale
+        out["kernels"][st] = {"n": n, "kernel_source_sha": kernel_source_sha(),
+                              "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                              "hbm_bytes_per_launch": fb + wb,
+                              "algorithmic_bytes_per_launch": BYTES_PER_NODE[st] * n * n,
+                              "fetch_kib_raw": v, "write_kib_raw": write[k]}
+    with open(TRAFFIC_FILE, "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def cpu_baseline(n, tau, steps, fields):
     import numpy as np
 
@@ -111,6 +181,9 @@ def cpu_baseline(n, tau, steps, fields):
 
 def main():
     args = parse()
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc, args.n)
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the sweep's multi-GPU slab decomposition is design-only).", file=sys.stderr)
@@ -122,6 +195,9 @@ def main():
     torch.cuda.set_device(0)
     n, tau = args.n, args.tau
     fields = workloads.shear_wave(n, 0.05)
+    if args.pmc_workload:
+        pmc_workload(oreg, torch, n, tau, fields)
+        return 0
     ms, diag = time_lattice(oreg, torch, n, tau, args.storage, args.steps, args.warmup, fields)
     if diag[5] != 0:
         raise RuntimeError("non-finite populations after the timed run")

@@ -62,40 +62,132 @@ __device__ __forceinline__ int wrap_sub(int v, int c, int n) {
 }
 
 // ---------------------------------------------------------------- sweep --
+// Launch shape per storage: nodes per thread (VX) and workgroup size.  One
+// node per thread keeps the FP64 and FP32 collisions at high occupancy; two
+// nodes per thread give the 16-bit formats 4-byte loads per lane.
+template <int ST> struct SweepShape { static constexpr int VX = 1, BS = 256; };
+template <> struct SweepShape<LB_F32S> { static constexpr int VX = 1, BS = 512; };
+template <> struct SweepShape<LB_F16S> { static constexpr int VX = 2, BS = 256; };
+template <> struct SweepShape<LB_BF16S> { static constexpr int VX = 2, BS = 256; };
+
+// Unaligned vector load (gfx950 global loads accept any 2-byte alignment).
+template <typename V, typename T>
+__device__ __forceinline__ V load_vec(const T* p) {
+  V v;
+  __builtin_memcpy(&v, p, sizeof(V));
+  return v;
+}
+
+// Pull f_i(x) = g_i(x - c_i) for VX consecutive nodes x0 .. x0+VX-1 of row y.
+// Threads away from the x edges use one vector load per plane; edge threads
+// wrap node by node.
+template <int ST, int VX>
+__device__ __forceinline__ void pull(const typename Storage<ST>::T* __restrict__ src,
+                                     const Geometry& g, int x0, int64_t r0, int64_t rm,
+                                     int64_t rp, typename Storage<ST>::R (&f)[VX][9]) {
+  using S = Storage<ST>;
+  using T = typename S::T;
+  typedef T V __attribute__((ext_vector_type(VX)));
+  const int64_t P = g.plane;
+  const int nx = g.nx;
+  if (x0 >= 1 && x0 + VX < nx) {
+    const V v0 = load_vec<V>(src + 0 * P + r0 + x0);
+    const V v1 = load_vec<V>(src + 1 * P + r0 + x0 - 1);
+    const V v2 = load_vec<V>(src + 2 * P + rm + x0);
+    const V v3 = load_vec<V>(src + 3 * P + r0 + x0 + 1);
+    const V v4 = load_vec<V>(src + 4 * P + rp + x0);
+    const V v5 = load_vec<V>(src + 5 * P + rm + x0 - 1);
+    const V v6 = load_vec<V>(src + 6 * P + rm + x0 + 1);
+    const V v7 = load_vec<V>(src + 7 * P + rp + x0 + 1);
+    const V v8 = load_vec<V>(src + 8 * P + rp + x0 - 1);
+#pragma unroll
+    for (int q = 0; q < VX; ++q) {
+      f[q][0] = S::load(v0[q]);
+      f[q][1] = S::load(v1[q]);
+      f[q][2] = S::load(v2[q]);
+      f[q][3] = S::load(v3[q]);
+      f[q][4] = S::load(v4[q]);
+      f[q][5] = S::load(v5[q]);
+      f[q][6] = S::load(v6[q]);
+      f[q][7] = S::load(v7[q]);
+      f[q][8] = S::load(v8[q]);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < VX; ++q) {
+      const int x = (x0 + q < nx) ? x0 + q : nx - 1;  // nodes past nx are not stored
+      const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
+      f[q][0] = S::load(src[0 * P + r0 + x]);
+      f[q][1] = S::load(src[1 * P + r0 + xm]);
+      f[q][2] = S::load(src[2 * P + rm + x]);
+      f[q][3] = S::load(src[3 * P + r0 + xp]);
+      f[q][4] = S::load(src[4 * P + rp + x]);
+      f[q][5] = S::load(src[5 * P + rm + xm]);
+      f[q][6] = S::load(src[6 * P + rm + xp]);
+      f[q][7] = S::load(src[7 * P + rp + xp]);
+      f[q][8] = S::load(src[8 * P + rp + xm]);
+    }
+  }
+}
+
+// Store the post-collision populations of VX nodes at x0.. (nontemporal: the
+// next sweep reads them back only after the whole lattice has streamed by).
+template <int ST, int VX>
+__device__ __forceinline__ void push_local(typename Storage<ST>::T* __restrict__ dst,
+                                           const Geometry& g, int x0, int64_t r0,
+                                           const typename Storage<ST>::R (&f)[VX][9]) {
+  using S = Storage<ST>;
+  using T = typename S::T;
+  typedef T V __attribute__((ext_vector_type(VX)));
+  const int64_t P = g.plane;
+  // Vector stores need sizeof(V) alignment: an even row length (VX = 2).
+  const bool aligned = (VX == 1) || ((((r0 + x0) | P) & (VX - 1)) == 0);
+  if (x0 + VX <= g.nx && aligned) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      V v;
+#pragma unroll
+      for (int q = 0; q < VX; ++q) v[q] = S::store(f[q][i]);
+      __builtin_nontemporal_store(v, reinterpret_cast<V*>(dst + i * P + r0 + x0));
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < VX; ++q) {
+      if (x0 + q < g.nx) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) dst[i * P + r0 + x0 + q] = S::store(f[q][i]);
+      }
+    }
+  }
+}
+
 template <int EQ, int COLL, int BC, int ST>
-__global__ __launch_bounds__(kThreads) void sweep_kernel(
+__global__ __launch_bounds__(SweepShape<ST>::BS) void sweep_kernel(
     const typename Storage<ST>::T* __restrict__ src, typename Storage<ST>::T* __restrict__ dst,
     Geometry g, Coef64 c, int nseg) {
   using S = Storage<ST>;
   using R = typename S::R;
+  constexpr int VX = SweepShape<ST>::VX, BS = SweepShape<ST>::BS;
   const int y = blockIdx.x / nseg;
-  const int x = (blockIdx.x - y * nseg) * kThreads + threadIdx.x;
-  if (x >= g.nx) return;
-  const int nx = g.nx, ny = g.ny;
-  const int xm = wrap_dec(x, nx), xp = wrap_inc(x, nx);
-  const int ym = wrap_dec(y, ny), yp = wrap_inc(y, ny);
-  const int64_t P = g.plane;
-  const int64_t r0 = (int64_t)y * nx, rm = (int64_t)ym * nx, rp = (int64_t)yp * nx;
-  // Pull f_i(x) = g_i(x - c_i).
-  R f[9];
-  f[0] = S::load(src[0 * P + r0 + x]);
-  f[1] = S::load(src[1 * P + r0 + xm]);
-  f[2] = S::load(src[2 * P + rm + x]);
-  f[3] = S::load(src[3 * P + r0 + xp]);
-  f[4] = S::load(src[4 * P + rp + x]);
-  f[5] = S::load(src[5 * P + rm + xm]);
-  f[6] = S::load(src[6 * P + rm + xp]);
-  f[7] = S::load(src[7 * P + rp + xp]);
-  f[8] = S::load(src[8 * P + rp + xm]);
-  if (BC == LB_BC_BOUNCEBACK && (x == 0 || x == nx - 1)) {
-    // Full-way bounce-back wall node: reverse every population.
-    R r[9];
-    unroll<0, 9>([&](auto I) { r[I.value] = f[opp_of(I.value)]; });
-    unroll<0, 9>([&](auto I) { dst[I.value * P + r0 + x] = S::store(r[I.value]); });
-    return;
+  const int x0 = ((blockIdx.x - y * nseg) * BS + threadIdx.x) * VX;
+  if (x0 >= g.nx) return;
+  const int ym = wrap_dec(y, g.ny), yp = wrap_inc(y, g.ny);
+  const int64_t r0 = (int64_t)y * g.nx, rm = (int64_t)ym * g.nx, rp = (int64_t)yp * g.nx;
+  R f[VX][9];
+  pull<ST, VX>(src, g, x0, r0, rm, rp, f);
+  const Coeffs<R> k(c);
+#pragma unroll
+  for (int q = 0; q < VX; ++q) {
+    if (BC == LB_BC_BOUNCEBACK && (x0 + q == 0 || x0 + q == g.nx - 1)) {
+      // Full-way bounce-back wall node: reverse every population.
+      R r[9];
+      unroll<0, 9>([&](auto I) { r[I.value] = f[q][opp_of(I.value)]; });
+      unroll<0, 9>([&](auto I) { f[q][I.value] = r[I.value]; });
+    } else {
+      collide<EQ, COLL, S::shifted>(f[q], k);
+    }
   }
-  collide<EQ, COLL, S::shifted>(f, Coeffs<R>(c));
-  unroll<0, 9>([&](auto I) { dst[I.value * P + r0 + x] = S::store(f[I.value]); });
+  push_local<ST, VX>(dst, g, x0, r0, f);
 }
 
 // ----------------------------------------------------------------- init --
@@ -306,14 +398,16 @@ unsigned int blocks_for(int64_t n) { return (unsigned int)((n + kThreads - 1) / 
 // ------------------------------------------------------------ launchers --
 hipError_t launch_sweep(int eq, int coll, int bc, int st, const void* src, void* dst,
                         const Geometry& g, const Coef64& c, hipStream_t s) {
-  const int nseg = (g.nx + kThreads - 1) / kThreads;
-  const unsigned int nblocks = (unsigned int)nseg * (unsigned int)g.ny;
   return with_storage(st, [&](auto ST) {
     using T = typename Storage<ST.value>::T;
+    constexpr int tile = SweepShape<ST.value>::VX * SweepShape<ST.value>::BS;
+    const int nseg = (g.nx + tile - 1) / tile;
+    const unsigned int nblocks = (unsigned int)nseg * (unsigned int)g.ny;
     return with_eq(eq, [&](auto EQ) {
       return with_coll(coll, [&](auto CO) {
         return with_bc(bc, [&](auto BC) {
-          sweep_kernel<EQ.value, CO.value, BC.value, ST.value><<<nblocks, kThreads, 0, s>>>(
+          sweep_kernel<EQ.value, CO.value, BC.value, ST.value>
+              <<<nblocks, SweepShape<ST.value>::BS, 0, s>>>(
               static_cast<const T*>(src), static_cast<T*>(dst), g, c, nseg);
           return hipGetLastError();
         });

@@ -78,7 +78,8 @@ typedef enum lb_status {
   LB_ENOMEM = -2,      /* a device allocation failed                          */
   LB_EDEVICE = -3,     /* any other HIP error, or no usable device            */
   LB_ESTATE = -4,      /* call not valid in the lattice's state (not inited)  */
-  LB_ENONFINITE = -5   /* lb_step with check_nonfinite found NaN/Inf          */
+  LB_ENONFINITE = -5,  /* lb_step with check_nonfinite found NaN/Inf          */
+  LB_EAGAIN = -6       /* server: no room / nothing ready now; retry later    */
 } lb_status;
 
 typedef struct lb_options {
@@ -181,6 +182,104 @@ const char* lb_status_string(lb_status s);
 /* Message of the last failing call on h, or of the calling thread's last
    failing call when h is NULL; "" if none.  Valid until the next call. */
 const char* lb_last_error(const lb_lattice* h);
+
+/* ------------------------------------------------------------------------
+ * Serving: many independent lattices resident on one GPU (continuous
+ * batching).
+ *
+ * A server owns a device arena of `memory_budget` bytes.  lb_server_submit
+ * admits a request at once when a slot and arena space are free (its
+ * footprint is 2 * 9 * sizeof(storage) + 24 bytes per node) and returns
+ * LB_EAGAIN otherwise, so the caller keeps the queue and retries as lattices
+ * retire.  lb_server_step advances every resident lattice by one time step per
+ * iteration with a single batched launch that covers all of them (each lattice
+ * runs the same per-node update as lb_step, Eqs. (6), (7) with the server's
+ * equilibrium and storage and the request's tau), and retires each lattice
+ * after its requested number of steps: its moments are gathered and copied to
+ * pinned host memory asynchronously.  lb_server_poll reports finished results,
+ * lb_server_fetch hands their moments to the caller.  A result does not depend
+ * on which other lattices shared the launches: the per-node arithmetic is that
+ * of a lattice running alone.
+ * ------------------------------------------------------------------------ */
+typedef struct lb_server lb_server;
+
+typedef struct lb_server_options {
+  int64_t memory_budget;      /* device bytes for resident lattices, > 0       */
+  int64_t pinned_bytes;       /* pinned host bytes for field uploads and
+                                 results (each side), > 0                      */
+  int max_active;             /* resident lattices at most, 1 .. 65536         */
+  lb_equilibrium equilibrium;
+  lb_storage storage;
+  double theta;               /* as in lb_options                              */
+  double rho0;                /* reference density of shifted storage          */
+  int device;                 /* -1: current device                            */
+} lb_server_options;
+
+typedef struct lb_request {
+  int64_t tag;                /* caller's identifier, reported with the result */
+  int nx, ny;                 /* lattice size, >= 1                            */
+  double tau;                 /* > 1/2                                         */
+  int64_t steps;              /* time steps to run, >= 1                       */
+  const double* rho;          /* host [ny][nx] initial fields (f = f^eq),     */
+  const double* ux;           /* copied during the call                        */
+  const double* uy;
+} lb_request;
+
+typedef struct lb_result {
+  int64_t tag;
+  int nx, ny;
+  int64_t steps;
+  double t_submit, t_done;    /* server clock (seconds, monotonic) at admission
+                                 and when the moments reached host memory      */
+} lb_result;
+
+typedef struct lb_server_stats {
+  int active;                 /* resident lattices being stepped               */
+  int retiring;               /* finished, moments in flight to the host       */
+  int ready;                  /* results waiting for lb_server_fetch           */
+  int64_t device_bytes_used;  /* arena bytes held                              */
+  int64_t launches;           /* batched sweeps launched                       */
+  int64_t node_updates;       /* sum over launches of the nodes they updated   */
+  double clock;               /* server clock now (seconds)                    */
+} lb_server_stats;
+
+/* Defaults: 16 GiB arena, 1 GiB pinned per side, 256 slots, guided, F32S,
+   theta 1/3, rho0 1, current device. */
+void lb_server_options_init(lb_server_options* opt);
+
+/* LB_EINVAL for invalid options (as lb_create_ex for the equilibrium, storage,
+   theta and rho0); LB_ENOMEM / LB_EDEVICE from HIP. */
+lb_status lb_server_create(const lb_server_options* opt, lb_server** out);
+
+/* Admit one request now.  LB_EAGAIN: no free slot, arena or pinned space at
+   the moment (nothing was kept; retry after lb_server_step / lb_server_poll).
+   LB_EINVAL: invalid request, non-finite field or rho <= 0, or a footprint
+   larger than the whole arena. */
+lb_status lb_server_submit(lb_server* s, const lb_request* req);
+
+/* Run up to n batched steps (fewer if no lattice is resident); retires
+   lattices as they finish.  Asynchronous: returns once the launches are
+   enqueued. */
+lb_status lb_server_step(lb_server* s, int64_t n);
+
+/* Oldest finished result whose moments are in host memory: fills *out and
+   returns LB_OK, or LB_EAGAIN if none is ready. */
+lb_status lb_server_poll(lb_server* s, lb_result* out);
+
+/* Copy the moments rho, ux, uy (host double out[3][ny][nx]) of the ready
+   result `tag` and release it.  LB_EINVAL if no ready result has that tag. */
+lb_status lb_server_fetch(lb_server* s, int64_t tag, double* out);
+
+lb_status lb_server_stats_get(lb_server* s, lb_server_stats* out);
+
+/* Wait for all enqueued work. */
+lb_status lb_server_sync(lb_server* s);
+
+/* Free the server (waits for its work).  NULL-safe. */
+lb_status lb_server_destroy(lb_server* s);
+
+/* Message of the last failing call on s ("" if none). */
+const char* lb_server_last_error(const lb_server* s);
 
 #ifdef __cplusplus
 }

@@ -391,6 +391,53 @@ __global__ __launch_bounds__(kThreads) void profile_kernel(const typename Storag
   out[x] = sum / g.ny;
 }
 
+// ------------------------------------------------------ batched sweep --
+__global__ __launch_bounds__(kThreads) void tile_map_kernel(const LatticeDesc* __restrict__ d,
+                                                            int n, int* __restrict__ map,
+                                                            int64_t tiles) {
+  const int64_t b = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (b >= tiles) return;
+  int lo = 0, hi = n - 1;  // last lattice whose first tile is <= b
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].tile_begin <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  map[b] = lo;
+}
+
+// Each workgroup updates kBatchTile consecutive nodes (row-major) of one
+// lattice, kBatchTile / kThreads nodes per thread, one node at a time with
+// per-node periodic wrap; the collision is the one of sweep_kernel.
+template <int EQ, int ST>
+__global__ __launch_bounds__(kThreads) void batched_sweep_kernel(const LatticeDesc* __restrict__ d,
+                                                                 const int* __restrict__ map,
+                                                                 int64_t T) {
+  using S = Storage<ST>;
+  using R = typename S::R;
+  using Tt = typename S::T;
+  const LatticeDesc& L = d[map[blockIdx.x]];
+  const int64_t first = ((int64_t)blockIdx.x - L.tile_begin) * kBatchTile;
+  const int64_t t = T - L.admit_T;
+  const Tt* __restrict__ src = static_cast<const Tt*>(L.buf[t & 1]);
+  Tt* __restrict__ dst = static_cast<Tt*>(L.buf[(t + 1) & 1]);
+  const Geometry g{L.nx, L.ny, L.plane};
+  const Coeffs<R> k(L.coef);
+#pragma unroll 1
+  for (int j = 0; j < kBatchTile / kThreads; ++j) {
+    const int64_t c = first + j * kThreads + threadIdx.x;
+    if (c >= g.plane) break;
+    const int y = (int)(c / g.nx);
+    const int x = (int)(c - (int64_t)y * g.nx);
+    const int ym = wrap_dec(y, g.ny), yp = wrap_inc(y, g.ny);
+    const int64_t r0 = (int64_t)y * g.nx, rm = (int64_t)ym * g.nx, rp = (int64_t)yp * g.nx;
+    R f[1][9];
+    pull<ST, 1>(src, g, x, r0, rm, rp, f);
+    collide<EQ, LB_COLL_OREG, S::shifted>(f[0], k);
+    push_local<ST, 1>(dst, g, x, r0, f);
+  }
+}
+
 unsigned int blocks_for(int64_t n) { return (unsigned int)((n + kThreads - 1) / kThreads); }
 
 }  // namespace
@@ -470,6 +517,24 @@ hipError_t launch_diagnostics(int st, const void* src, double* partials, double*
     if (e != hipSuccess) return e;
     diag_final_kernel<<<1, kThreads, 0, s>>>(partials, kDiagBlocks, out);
     return hipGetLastError();
+  });
+}
+
+hipError_t launch_tile_map(const LatticeDesc* d, int n, int* tile_map, int64_t tiles,
+                           hipStream_t s) {
+  tile_map_kernel<<<blocks_for(tiles), kThreads, 0, s>>>(d, n, tile_map, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched_sweep(int eq, int st, const LatticeDesc* d, const int* tile_map,
+                                int64_t tiles, int64_t T, hipStream_t s) {
+  if (tiles <= 0) return hipSuccess;
+  return with_storage(st, [&](auto ST) {
+    return with_eq(eq, [&](auto EQ) {
+      batched_sweep_kernel<EQ.value, ST.value><<<(unsigned int)tiles, kThreads, 0, s>>>(
+          d, tile_map, T);
+      return hipGetLastError();
+    });
   });
 }
 

@@ -55,4 +55,28 @@ hipError_t launch_diagnostics(int st, const void* src, double* partials, double*
 hipError_t launch_profile(int st, const void* src, double* out, const Geometry& g,
                           const Coef64& c, hipStream_t s);
 
+// ------------------------------------------------------------ serving --
+// One resident lattice of a server, as the batched sweep reads it.
+struct LatticeDesc {
+  void* buf[2];        // A/B population buffers
+  double* fields;      // 3 * plane FP64: initial fields, later the result moments
+  int nx, ny;
+  int64_t plane;       // nx * ny
+  int64_t admit_T;     // server step counter when admitted (local time = T - admit_T)
+  int64_t tile_begin;  // first tile of this lattice in the batched launch
+  Coef64 coef;
+};
+
+// Nodes per workgroup tile of the batched sweep.
+constexpr int kBatchTile = 1024;
+
+// tile_map[b] = index of the lattice that owns tile b (after the descriptors
+// are in device memory).
+hipError_t launch_tile_map(const LatticeDesc* d, int n, int* tile_map, int64_t tiles,
+                           hipStream_t s);
+
+// One time step of every lattice in d[0..n): tiles workgroups, global step T.
+hipError_t launch_batched_sweep(int eq, int st, const LatticeDesc* d, const int* tile_map,
+                                int64_t tiles, int64_t T, hipStream_t s);
+
 }  // namespace oreg

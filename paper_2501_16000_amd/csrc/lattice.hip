@@ -453,6 +453,7 @@ const char* lb_status_string(lb_status s) {
     case LB_EDEVICE: return "LB_EDEVICE: HIP error or no device";
     case LB_ESTATE: return "LB_ESTATE: lattice not initialized";
     case LB_ENONFINITE: return "LB_ENONFINITE: non-finite populations";
+    case LB_EAGAIN: return "LB_EAGAIN: not now, retry later";
   }
   return "unknown lb_status";
 }

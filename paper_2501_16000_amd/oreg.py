@@ -40,7 +40,7 @@ LB_EQ_GUIDED, LB_EQ_POLY2 = 0, 1
 LB_F64, LB_F32S, LB_F16S, LB_BF16S = 0, 1, 2, 3
 LB_COLL_OREG, LB_COLL_BGK = 0, 1
 LB_BC_PERIODIC, LB_BC_BOUNCEBACK = 0, 1
-LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ESTATE, LB_ENONFINITE = 0, -1, -2, -3, -4, -5
+LB_OK, LB_EINVAL, LB_ENOMEM, LB_EDEVICE, LB_ESTATE, LB_ENONFINITE, LB_EAGAIN = 0, -1, -2, -3, -4, -5, -6
 
 EQUILIBRIA = {"guided": LB_EQ_GUIDED, "poly2": LB_EQ_POLY2}
 STORAGES = {"f64": LB_F64, "f32s": LB_F32S, "f16s": LB_F16S, "bf16s": LB_BF16S}

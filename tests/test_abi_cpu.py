@@ -37,7 +37,8 @@ def test_library_exports_every_declared_symbol():
     exported = set(re.findall(r"\bT (lb_[a-z_0-9]+)$", out, flags=re.M))
     missing = [n for n in declared_functions() if n not in exported]
     assert not missing, f"declared but not exported: {missing}"
-    assert sorted(m.EXPORTED) == declared_functions()
+    from paper_2501_16000_amd import serve
+    assert sorted(m.EXPORTED + serve.EXPORTED) == declared_functions()
 
 
 def test_options_defaults_and_struct_layout():
@@ -93,7 +94,8 @@ def test_null_arguments():
 
 def test_status_strings():
     m = oreg()
-    for code in (m.LB_OK, m.LB_EINVAL, m.LB_ENOMEM, m.LB_EDEVICE, m.LB_ESTATE, m.LB_ENONFINITE):
+    for code in (m.LB_OK, m.LB_EINVAL, m.LB_ENOMEM, m.LB_EDEVICE, m.LB_ESTATE, m.LB_ENONFINITE,
+                 m.LB_EAGAIN):
         assert m.lb_status_string(code).decode().startswith("LB_")
     assert m.lb_status_string(42) == b"unknown lb_status"
 
@@ -107,3 +109,21 @@ def test_valid_create_without_device_reports_edevice():
     assert m.lb_create(8, 8, 0.8, 1 / 3, m.LB_EQ_GUIDED, ctypes.byref(h)) == m.LB_EDEVICE
     assert h.value is None
     assert "device" in m.lb_last_error(None).decode()
+
+
+def test_server_options_defaults_and_validation():
+    from paper_2501_16000_amd import serve
+    m = oreg()
+    o = serve.lb_server_options()
+    serve.lb_server_options_init(ctypes.byref(o))
+    assert o.memory_budget == 16 << 30 and o.pinned_bytes == 1 << 30 and o.max_active == 256
+    assert o.storage == m.LB_F32S and o.equilibrium == m.LB_EQ_GUIDED and o.device == -1
+    h = ctypes.c_void_p()
+    for field, bad in (("memory_budget", 0), ("max_active", 0), ("max_active", 70000),
+                       ("storage", 7), ("theta", 1.5), ("rho0", -1.0)):
+        o2 = serve.lb_server_options()
+        serve.lb_server_options_init(ctypes.byref(o2))
+        setattr(o2, field, bad)
+        assert serve.lb_server_create(ctypes.byref(o2), ctypes.byref(h)) == m.LB_EINVAL
+    assert serve.lb_server_destroy(None) == m.LB_OK
+    assert serve.lb_server_step(None, 1) == m.LB_EINVAL

@@ -47,6 +47,10 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=10,
                    help="oracle steps on the full lattice for the CPU baseline")
+    p.add_argument("--serving-requests", type=int, default=2000,
+                   help="requests of the serving stream (0 skips the serving measurement)")
+    p.add_argument("--serving-plain-sample", type=int, default=150,
+                   help="requests of the stream also run one lattice per launch in FP64")
     p.add_argument("--pmc-workload", action="store_true",
                    help="only run a few sweeps per storage plus a 1 GiB device copy "
                         "(the workload profiled with rocprofv3 --pmc)")
@@ -164,6 +168,76 @@ def summarize_pmc(fetch_csv, write_csv, n):
     print(json.dumps(out, indent=1))
 
 
+def serving_bench(oreg, count, plain_sample):
+    """The serving stream: rotated shear waves, N log-uniform in 32..1024,
+    tau ~ U[0.52, 1.2], u0 ~ U[0.005, 0.05], steps ~ U{200..5000}, FP32S.
+
+    1. capacity: every request available at once (saturated server);
+    2. Poisson arrivals at 0.8 x that capacity: p50 / p99 latency (arrival ->
+       moments in host memory) and aggregate MLUPS over the run;
+    3. the plain path on the first requests of the same stream: one FP64
+       lattice per request, lb_step over all its steps, one lattice at a time;
+       and the decay-rate error of the served (FP32S) results against it."""
+    import math
+
+    import numpy as np
+
+    from paper_2501_16000_amd import serve, workloads
+    base = workloads.serving_requests(count=count, seed=16000, rate_hz=1.0)
+    lup = np.array([r.n * r.n * r.steps for r in base], dtype=float)
+    with serve.Server(memory_budget=16 << 30, max_active=256, storage="f32s") as srv:
+        sat = serve.run_stream(srv, base, realtime=False)
+    capacity = sat.node_updates / sat.wall_s
+    rate = 0.8 * capacity / lup.mean()
+    stream = workloads.serving_requests(count=count, seed=16000, rate_hz=rate)
+    with serve.Server(memory_budget=16 << 30, max_active=256, storage="f32s") as srv:
+        rep = serve.run_stream(srv, stream, realtime=True, keep_results=False)
+    # plain one-lattice-per-launch FP64 path on a sample, and decay errors
+    sample = base[:plain_sample]
+    served = {}
+    with serve.Server(memory_budget=16 << 30, max_active=256, storage="f32s") as srv:
+        served = serve.run_stream(srv, sample, realtime=False, keep_results=True).results
+    t0 = time.perf_counter()
+    plain_lup, plain = 0, {}
+    for r in sample:
+        with oreg.Lattice(r.n, r.n, r.tau, 1.0 / 3.0) as lat:
+            lat.init(*workloads.shear_wave(r.n, r.u0))
+            lat.step(r.steps)
+            plain[r.rid] = lat.moments()
+        plain_lup += r.n * r.n * r.steps
+    plain_s = time.perf_counter() - t0
+    errs = []
+    for r in sample:
+        e_perp, phase = workloads.shear_wave_projection(r.n)
+
+        def amp(m):
+            return abs(((e_perp[0] * m[1] + e_perp[1] * m[2]) * phase).sum())
+
+        a0 = amp(np.stack(workloads.shear_wave(r.n, r.u0)))
+        ln_ref = math.log(a0 / amp(plain[r.rid]))
+        # well-conditioned decays only: at least 5 % and the wave still at
+        # 1e-4 of its start (below that the FP32 storage noise floor decides)
+        if 0.05 <= ln_ref <= math.log(1e4):
+            errs.append(abs(math.log(a0 / amp(served[r.rid])) / ln_ref - 1))
+    return {
+        "workload": f"{count} rotated shear-wave requests, N log-uniform 32..1024, "
+                    "tau U[0.52,1.2], u0 U[0.005,0.05], steps U{200..5000}, FP32S storage, "
+                    "guided equilibrium, Poisson arrivals at 0.8 x measured capacity",
+        "rate_hz": round(rate, 2),
+        "p50_latency_s": round(rep.percentile(50), 4),
+        "p99_latency_s": round(rep.percentile(99), 4),
+        "aggregate_mlups": round(rep.mlups, 1),
+        "wall_s": round(rep.wall_s, 2),
+        "saturated_mlups": round(sat.mlups, 1),
+        "launches": rep.launches,
+        "plain_f64_one_lattice_per_launch_mlups": round(plain_lup / plain_s / 1e6, 1),
+        "plain_sample": f"first {len(sample)} requests of the stream",
+        "served_vs_plain_decay_rate_error_max": float(max(errs)) if errs else None,
+        "decay_rate_samples": len(errs),
+        "decay_rate_window": "0.05 <= ln(a0/aT) <= ln(1e4) of the FP64 run",
+    }
+
+
 def cpu_baseline(n, tau, steps, fields):
     import numpy as np
 
@@ -246,6 +320,8 @@ def main():
                      "algorithmic_bytes_per_launch": alg_bytes},
         "variants": variants,
     }
+    if args.serving_requests > 0:
+        line["serving"] = serving_bench(oreg, args.serving_requests, args.serving_plain_sample)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n, tau, args.cpu_steps, fields)
     print(json.dumps(line), flush=True)

@@ -215,7 +215,7 @@ class _FieldPrefetch:
 
 
 def run_stream(server: Server, requests, realtime: bool = True, steps_per_call: int = 4,
-               keep_results: bool = False) -> StreamReport:
+               keep_results: bool = False, timeout_s: float = 600.0) -> StreamReport:
     """Drive ``requests`` (workloads.ServingRequest) through ``server``.
 
     Requests become visible at their arrival time (``realtime``) or all at
@@ -234,6 +234,9 @@ def run_stream(server: Server, requests, realtime: bool = True, steps_per_call: 
     try:
         while done < len(pending):
             now = time.perf_counter() - t0
+            if now > timeout_s:
+                raise TimeoutError(f"serving stream unfinished after {timeout_s} s "
+                                   f"({done}/{len(pending)} done)")
             while i < len(pending) and (not realtime or pending[i].arrival_s <= now):
                 queue.append(pending[i])
                 arrival_wall[pending[i].rid] = t0 + (pending[i].arrival_s if realtime else 0.0)

@@ -29,7 +29,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS (FP64 vs FP32/BF16 storage) at % HBM roofline; p50/p99 latency batched"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector
+FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector
+VALU_PEAK = 256 * 4 * 16 * 2.4e9  # lane-instructions/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 BYTES_PER_NODE = {"f64": 144, "f32s": 72, "f16s": 36, "bf16s": 36}
+# Time steps per fused launch (kernels.hip FusedLevels) and the algorithmic
+# flops of one guided-equilibrium OReg node update as implemented in
+# d2q9.hpp::collide (FMA = 2, the one division = 1): moments 22, equilibrium
+# 28, stress + reconstruction + relaxation 77.
+FUSED_K = {"f64": 6, "f32s": 6, "f16s": 1, "bf16s": 1}
+FLOPS_PER_UPDATE = 127
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_4096.json")
 
 
@@ -60,13 +69,14 @@ def parse():
     return p.parse_args()
 
 
-def time_lattice(oreg, torch, n, tau, storage, steps, warmup, fields):
-    """Return (elapsed_ms, steps) of `steps` sweeps timed with HIP events on
-    the stream the sweep is launched on."""
+def time_lattice(oreg, torch, n, tau, storage, steps, warmup, fields, fuse_steps=0):
+    """Return (elapsed_ms, diagnostics) of `steps` time steps timed with HIP
+    events on the stream the sweeps are launched on."""
     stream = torch.cuda.Stream()  # default priority
     rho0 = 1.0
     with torch.cuda.stream(stream), \
-            oreg.Lattice(n, n, tau, 1.0 / 3.0, storage=storage, rho0=rho0, stream=stream) as lat:
+            oreg.Lattice(n, n, tau, 1.0 / 3.0, storage=storage, rho0=rho0, stream=stream,
+                         fuse_steps=fuse_steps) as lat:
         lat.init(*fields)
         lat.step(warmup)
         torch.cuda.synchronize()
@@ -81,7 +91,7 @@ def time_lattice(oreg, torch, n, tau, storage, steps, warmup, fields):
     return ms, diag
 
 
-def load_traffic(storage, n, nbytes_alg):
+def load_traffic(storage, n, nbytes_alg, fused=False):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     covers this kernel build; else None."""
     try:
@@ -89,7 +99,7 @@ def load_traffic(storage, n, nbytes_alg):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    entry = t.get("kernels", {}).get(storage)
+    entry = t.get("kernels", {}).get(("fused_" if fused else "") + storage)
     if not entry or entry.get("n") != n or entry.get("kernel_source_sha") != kernel_source_sha():
         return None
     return entry.get("hbm_bytes_per_launch")
@@ -111,7 +121,8 @@ def pmc_workload(oreg, torch, n, tau, fields):
     """A few sweeps per storage and one plain 1 GiB device-to-device copy, the
     calibration of the HBM counters."""
     for st in ("f64", "f32s", "bf16s"):
-        time_lattice(oreg, torch, n, tau, st, 5, 2, fields)
+        time_lattice(oreg, torch, n, tau, st, 12, 0, fields)              # fused launches
+        time_lattice(oreg, torch, n, tau, st, 5, 2, fields, fuse_steps=1)  # single steps
     src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     src.fill_(1)
@@ -151,14 +162,16 @@ def summarize_pmc(fetch_csv, write_csv, n):
            "kernel_source_sha": kernel_source_sha(), "kernels": {}}
     sts = {"Storage<0>": "f64", "Storage<1>": "f32s", "Storage<2>": "f16s", "Storage<3>": "bf16s"}
     for k, v in fetch.items():
-        if "sweep_kernel" not in k:
+        if "sweep_kernel" not in k or "batched" in k:
             continue
         st = next((name for tag, name in sts.items() if tag in k), None)
         if st is None or k not in write:
             continue
         fb = v * 1024.0 * f_scale
         wb = write[k] * 1024.0 * w_scale
-        out["kernels"][st] = {"n": n, "kernel_source_sha": kernel_source_sha(),
+        key = ("fused_" if "fused_sweep_kernel" in k else "") + st
+        out["kernels"][key] = {"n": n, "kernel_source_sha": kernel_source_sha(),
+                               "kernel": k.split("(")[0],
                               "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
                               "hbm_bytes_per_launch": fb + wb,
                               "algorithmic_bytes_per_launch": BYTES_PER_NODE[st] * n * n,
@@ -278,10 +291,43 @@ def main():
     cells = n * n
     sec = ms / 1e3
     mlups = cells * args.steps / sec / 1e6
-    per_launch_s = sec / args.steps
+    K = FUSED_K[args.storage]
     alg_bytes = BYTES_PER_NODE[args.storage] * cells
-    achieved = alg_bytes / per_launch_s / 1e9
-    traffic = load_traffic(args.storage, n, alg_bytes)
+    if K > 1:
+        # the dominant kernel: K steps per launch; time whole launches only
+        nl = max(1, args.steps // K)
+        fms, _ = time_lattice(oreg, torch, n, tau, args.storage, nl * K, K, fields)
+        per_launch_s = fms / 1e3 / nl
+        flops = FLOPS_PER_UPDATE * K * cells
+        peak = FP64_PEAK_TFLOPS if args.storage == "f64" else FP32_PEAK_TFLOPS
+        achieved = flops / per_launch_s / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": peak,
+                    "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                    "traffic": load_traffic(args.storage, n, alg_bytes, fused=True),
+                    "kernel": f"fused_sweep_kernel<K={K}, guided, OReg, periodic, {args.storage}>",
+                    "launch_ms": round(per_launch_s * 1e3, 4),
+                    "node_updates_per_launch": K * cells,
+                    "flops_per_node_update": FLOPS_PER_UPDATE,
+                    "hbm_algorithmic_GBs": round(alg_bytes / per_launch_s / 1e9, 1)}
+    else:
+        per_launch_s = sec / args.steps
+        achieved = alg_bytes / per_launch_s / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": load_traffic(args.storage, n, alg_bytes),
+                    "kernel": f"sweep_kernel<guided, OReg, periodic, {args.storage}>",
+                    "algorithmic_bytes_per_launch": alg_bytes}
+    # the single-step sweep of the same workload (one launch per step)
+    sms, _ = time_lattice(oreg, torch, n, tau, args.storage, min(args.steps, 300), 10, fields,
+                          fuse_steps=1)
+    s_launch = sms / 1e3 / min(args.steps, 300)
+    s_ach = alg_bytes / s_launch / 1e9
+    single = {"value": round(cells / s_launch / 1e6, 1), "unit": "MLUPS",
+              "kernel": f"sweep_kernel<guided, OReg, periodic, {args.storage}>",
+              "roofline": {"bound": "hbm", "achieved": round(s_ach, 1), "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": round(s_ach / HBM_PEAK_GBS, 4),
+                           "traffic": load_traffic(args.storage, n, alg_bytes),
+                           "algorithmic_bytes_per_launch": alg_bytes}}
 
     variants = {}
     for st in [s for s in args.variants.split(",") if s and s != args.storage]:
@@ -313,11 +359,8 @@ def main():
                                f"along atan(1/2), guided equilibrium, theta=1/3, tau={tau}, "
                                f"{args.storage} storage, one lattice per launch",
                    "nx": n, "ny": n, "tau": tau, "storage": args.storage},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic,
-                     "kernel": "sweep_kernel",
-                     "algorithmic_bytes_per_launch": alg_bytes},
+        "roofline": roofline,
+        "single_step": single,
         "variants": variants,
     }
     if args.serving_requests > 0:

@@ -98,16 +98,22 @@ typedef struct lb_options {
                                  kept alive until lb_destroy returns           */
   int device;                 /* HIP device ordinal; -1: current device         */
   int check_nonfinite;        /* nonzero: lb_step scans for NaN/Inf afterwards  */
+  int fuse_steps;             /* 0: lb_step advances several time steps per
+                                 launch where it can (register-resident
+                                 multi-step sweep; same result bit for bit);
+                                 1: one sweep launch per time step             */
 } lb_options;
 
 /* Defaults: 0 x 0, tau 1, theta 1/3, guided, LB_F64, OReg, periodic, rho0 1,
-   own stream (use_stream 0), current device, no checks.  NULL-safe. */
+   own stream (use_stream 0), current device, no checks, fused steps.
+   NULL-safe. */
 void lb_options_init(lb_options* opt);
 
 /* FP64 periodic OReg lattice on the current device with its own stream.
    LB_EINVAL: nx or ny < 1, too large, tau or theta not finite, tau <= 1/2,
    guided with theta outside (0, 1), polynomial with |theta - 1/3| > 1e-12,
-   unknown enum, out == NULL.  LB_ENOMEM / LB_EDEVICE from HIP. */
+   unknown enum, fuse_steps not 0 or 1, out == NULL.  LB_ENOMEM / LB_EDEVICE
+   from HIP. */
 lb_status lb_create(int nx, int ny, double tau, double theta, lb_equilibrium eq,
                     lb_lattice** out);
 

@@ -16,8 +16,9 @@
 //       S_xx = -S_yy = s = ((f1 + f3) - (f2 + f4) - rho (ux^2 - uy^2)) / 2,
 //       S_xy = (f5 + f7) - (f6 + f8) - rho ux uy;
 //   * with a trace-free S, (C C - C^2/2 I):S = s (Cx^2 - Cy^2) + 2 S_xy Cx Cy,
-//     C = c_i - u, and f^post_i = f^eq_i (1 + kappa b_i) with
-//     kappa = (1 - 1/tau) / (2 rho theta^2).
+//     C = c_i - u, and f^post_i = f^eq_i + f^eq_i kappa b_i with
+//     kappa = (1 - 1/tau) / (2 rho theta^2); kappa b_i is assembled from
+//     per-axis factors (3 x-values, 3 y-values);
 //   * shifted storage carries df_i = f_i - w_i rho0; the axis and diagonal
 //     weights are equal in pairs, so s and S_xy need no shift, and
 //     f^eq_i - w_i rho0 is formed from small differences to keep FP32
@@ -100,9 +101,10 @@ struct Coef64 {
 template <typename R>
 struct Coeffs {
   R theta, a0, a1, kappa0, omega, rho0;
+  R r0a0, r0a1;  // rho0 a0, rho0 a1
   __host__ __device__ explicit Coeffs(const Coef64& c)
       : theta((R)c.theta), a0((R)c.a0), a1((R)c.a1), kappa0((R)c.kappa0),
-        omega((R)c.omega), rho0((R)c.rho0) {}
+        omega((R)c.omega), rho0((R)c.rho0), r0a0((R)(c.rho0 * c.a0)), r0a1((R)(c.rho0 * c.a1)) {}
 };
 
 // Per-axis factor selected by the velocity component c (-1, 0, +1).
@@ -121,33 +123,55 @@ __host__ __device__ __forceinline__ R peculiar(R u) {
   else return R(-1) - u;
 }
 
+// a * b + c with one rounding.  The collision spells out every fused
+// multiply-add and is compiled with contraction off, so every kernel that
+// inlines it (plain sweep, multi-step sweep, batched serving sweep) rounds
+// identically and their results agree bit for bit.
+__host__ __device__ __forceinline__ double fmadd(double a, double b, double c) {
+  return __builtin_fma(a, b, c);
+}
+__host__ __device__ __forceinline__ float fmadd(float a, float b, float c) {
+  return __builtin_fmaf(a, b, c);
+}
+
 // Equilibrium of one node: feq_i (full value) and deq_i = feq_i - w_i rho0
-// (deq = feq when unshifted).  drho = rho - rho0 (= rho when unshifted).
+// (deq = feq when unshifted).  drho = rho - rho0 (= rho when unshifted);
+// uxx = ux^2, uyy = uy^2.
 template <int EQ, bool SHIFTED, typename R>
-__host__ __device__ __forceinline__ void equilibrium(R drho, R rho, R ux, R uy, const Coeffs<R>& k,
-                                            R (&feq)[9], R (&deq)[9]) {
-  const R uxx = ux * ux, uyy = uy * uy;
+__host__ __device__ __forceinline__ void equilibrium(R drho, R rho, R ux, R uy, R uxx, R uyy,
+                                                     const Coeffs<R>& k, R (&feq)[9],
+                                                     R (&deq)[9]) {
+#pragma clang fp contract(off)
   if constexpr (EQ == LB_EQ_GUIDED) {
-    // Per-axis factors of Eq. (11) as rest value + small difference.
+    // Per-axis factors of Eq. (11) as rest value + small difference:
+    // Psi(-1) = a1 + (u^2 - u)/2, Psi(0) = a0 - u^2, Psi(+1) = a1 + (u^2 + u)/2.
     const R hx = R(0.5) * uxx, hy = R(0.5) * uyy;
-    const R dXm = hx - R(0.5) * ux, dX0 = -uxx, dXp = hx + R(0.5) * ux;
-    const R dYm = hy - R(0.5) * uy, dY0 = -uyy, dYp = hy + R(0.5) * uy;
+    const R dXm = fmadd(R(-0.5), ux, hx), dX0 = -uxx, dXp = fmadd(R(0.5), ux, hx);
+    const R dYm = fmadd(R(-0.5), uy, hy), dY0 = -uyy, dYp = fmadd(R(0.5), uy, hy);
     const R Xm = k.a1 + dXm, X0 = k.a0 + dX0, Xp = k.a1 + dXp;
     const R Ym = k.a1 + dYm, Y0 = k.a0 + dY0, Yp = k.a1 + dYp;
-    unroll<0, 9>([&](auto I) {
-      constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
-      const R X = pick<cx>(Xm, X0, Xp), Y = pick<cy>(Ym, Y0, Yp);
-      const R XY = X * Y;
-      feq[I.value] = rho * XY;
-      if constexpr (SHIFTED) {
-        const R dX = pick<cx>(dXm, dX0, dXp), dY = pick<cy>(dYm, dY0, dYp);
-        const R ax = (cx == 0) ? k.a0 : k.a1;
-        // rho X Y - rho0 ax ay = drho X Y + rho0 (dX Y + ax dY)
-        deq[I.value] = drho * XY + k.rho0 * (dX * Y + ax * dY);
-      } else {
+    // feq_i = (rho X) Y
+    const R rXm = rho * Xm, rX0 = rho * X0, rXp = rho * Xp;
+    if constexpr (SHIFTED) {
+      // deq_i = rho X Y - rho0 ax ay = drho X Y + (rho0 dX) Y + (rho0 ax) dY
+      const R r0dXm = k.rho0 * dXm, r0dX0 = k.rho0 * dX0, r0dXp = k.rho0 * dXp;
+      const R a0dYm = k.r0a0 * dYm, a0dY0 = k.r0a0 * dY0, a0dYp = k.r0a0 * dYp;
+      const R a1dYm = k.r0a1 * dYm, a1dY0 = k.r0a1 * dY0, a1dYp = k.r0a1 * dYp;
+      unroll<0, 9>([&](auto I) {
+        constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
+        const R X = pick<cx>(Xm, X0, Xp), Y = pick<cy>(Ym, Y0, Yp);
+        const R XY = X * Y;
+        feq[I.value] = pick<cx>(rXm, rX0, rXp) * Y;
+        const R adY = (cx == 0) ? pick<cy>(a0dYm, a0dY0, a0dYp) : pick<cy>(a1dYm, a1dY0, a1dYp);
+        deq[I.value] = fmadd(drho, XY, fmadd(pick<cx>(r0dXm, r0dX0, r0dXp), Y, adY));
+      });
+    } else {
+      unroll<0, 9>([&](auto I) {
+        constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
+        feq[I.value] = pick<cx>(rXm, rX0, rXp) * pick<cy>(Ym, Y0, Yp);
         deq[I.value] = feq[I.value];
-      }
-    });
+      });
+    }
   } else {
     // Polynomial equilibrium at theta0 = 1/3: rho W_i (1 + P_i),
     // P_i = 3 c.u + 9/2 (c.u)^2 - 3/2 u^2.
@@ -162,10 +186,10 @@ __host__ __device__ __forceinline__ void equilibrium(R drho, R rho, R ux, R uy, 
       const R W = ((cx == 0) ? k.a0 : k.a1) * ((cy == 0) ? k.a0 : k.a1);
       R P;
       if constexpr (cx == 0 && cy == 0) P = -u2h;
-      else P = cu * (R(3) + R(4.5) * cu) - u2h;
+      else P = fmadd(cu, fmadd(R(4.5), cu, R(3)), -u2h);
       const R rW = rho * W;
-      feq[I.value] = rW + rW * P;
-      if constexpr (SHIFTED) deq[I.value] = drho * W + rW * P;
+      feq[I.value] = fmadd(rW, P, rW);
+      if constexpr (SHIFTED) deq[I.value] = fmadd(drho, W, rW * P);
       else deq[I.value] = feq[I.value];
     });
   }
@@ -175,33 +199,46 @@ __host__ __device__ __forceinline__ void equilibrium(R drho, R rho, R ux, R uy, 
 // by w_i rho0 when SHIFTED) and receives the post-collision ones (same shift).
 template <int EQ, int COLL, bool SHIFTED, typename R>
 __host__ __device__ __forceinline__ void collide(R (&f)[9], const Coeffs<R>& k) {
+#pragma clang fp contract(off)
   // Eq. (2a).  Sum w_i = 1 and sum w_i c_i = 0, so the shift only enters rho.
-  const R drho = f[0] + ((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[7]) + (f[6] + f[8]));
-  const R jx = (f[1] - f[3]) + (f[5] - f[7]) + (f[8] - f[6]);
-  const R jy = (f[2] - f[4]) + (f[5] - f[7]) + (f[6] - f[8]);
+  const R s13 = f[1] + f[3], s24 = f[2] + f[4], s57 = f[5] + f[7], s68 = f[6] + f[8];
+  const R drho = f[0] + (s13 + s24) + (s57 + s68);
+  const R d57 = f[5] - f[7];
+  const R jx = (f[1] - f[3]) + d57 + (f[8] - f[6]);
+  const R jy = (f[2] - f[4]) + d57 + (f[6] - f[8]);
   const R rho = SHIFTED ? k.rho0 + drho : drho;
   const R inv = R(1) / rho;
   const R ux = jx * inv, uy = jy * inv;
+  const R uxx = ux * ux, uyy = uy * uy;
 
   R feq[9], deq[9];
-  equilibrium<EQ, SHIFTED>(drho, rho, ux, uy, k, feq, deq);
+  equilibrium<EQ, SHIFTED>(drho, rho, ux, uy, uxx, uyy, k, feq, deq);
 
   if constexpr (COLL == LB_COLL_BGK) {
     // Eq. (1): f + (f^eq - f) / tau (the shift cancels in the difference).
-    unroll<0, 9>([&](auto I) { f[I.value] = f[I.value] + k.omega * (deq[I.value] - f[I.value]); });
+    unroll<0, 9>([&](auto I) { f[I.value] = fmadd(k.omega, deq[I.value] - f[I.value], f[I.value]); });
     return;
   } else {
-    // Trace-free non-equilibrium stress of Eq. (6) from second moments.
-    const R s = R(0.5) * (((f[1] + f[3]) - (f[2] + f[4])) - rho * (ux * ux - uy * uy));
-    const R sxy = ((f[5] + f[7]) - (f[6] + f[8])) - rho * (ux * uy);
-    const R two_sxy = sxy + sxy;
+    // Trace-free non-equilibrium stress of Eq. (6) from second moments:
+    // S_xx = -S_yy = s, S_xy.
+    const R s = R(0.5) * fmadd(-rho, uxx - uyy, s13 - s24);
+    const R sxy = fmadd(-rho, ux * uy, s57 - s68);
+    // Eqs. (6), (7): f^post_i = f^eq_i + kappa f^eq_i [s (Cx^2 - Cy^2) + 2 S_xy Cx Cy],
+    // kappa = (1 - 1/tau)/(2 rho theta^2), C = c_i - u.  With ks = kappa s and
+    // kt = 2 kappa S_xy the bracket splits into per-axis factors:
+    // kappa [..] = ks Cx^2 - ks Cy^2 + (kt Cx) Cy.
     const R kappa = k.kappa0 * inv;
-    // Eqs. (6), (7): f^post_i = f^eq_i + kappa f^eq_i b_i.
+    const R ks = kappa * s, kt = kappa * (sxy + sxy);
+    const R Cxm = R(-1) - ux, Cx0 = -ux, Cxp = R(1) - ux;
+    const R Cym = R(-1) - uy, Cy0 = -uy, Cyp = R(1) - uy;
+    const R axm = (ks * Cxm) * Cxm, ax0 = (ks * Cx0) * Cx0, axp = (ks * Cxp) * Cxp;
+    const R bym = (ks * Cym) * Cym, by0 = (ks * Cy0) * Cy0, byp = (ks * Cyp) * Cyp;
+    const R txm = kt * Cxm, tx0 = kt * Cx0, txp = kt * Cxp;
     unroll<0, 9>([&](auto I) {
       constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
-      const R Cx = peculiar<cx>(ux), Cy = peculiar<cy>(uy);
-      const R b = s * (Cx * Cx - Cy * Cy) + two_sxy * (Cx * Cy);
-      f[I.value] = deq[I.value] + (kappa * feq[I.value]) * b;
+      const R term = fmadd(pick<cx>(txm, tx0, txp), pick<cy>(Cym, Cy0, Cyp),
+                           pick<cx>(axm, ax0, axp) - pick<cy>(bym, by0, byp));
+      f[I.value] = fmadd(feq[I.value], term, deq[I.value]);
     });
   }
 }

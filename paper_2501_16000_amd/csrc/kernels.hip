@@ -190,6 +190,142 @@ __global__ __launch_bounds__(SweepShape<ST>::BS) void sweep_kernel(
   push_local<ST, VX>(dst, g, x0, r0, f);
 }
 
+// ------------------------------------------------ multi-step (fused) sweep --
+// K time steps per launch.  Each wavefront owns a strip of 64 columns and
+// marches down H output rows; lane l holds column X0 - K + l.  The rows of
+// time level 0 come from memory; level k + 1 of row y is computed from the
+// last three rows of level k (a sliding window kept in registers), the x
+// neighbours arrive by one-lane DPP shifts.  Every level loses one lane on
+// each side, so the 64 - 2K middle lanes of level K are stored.  The rows
+// needed above and below the strip's H rows (K on each side) are recomputed
+// by the neighbouring strips.  Between levels the populations are rounded
+// through the storage format, so the result equals K single-step sweeps bit
+// for bit.
+constexpr int kFusedRows = 64;  // output rows per wavefront
+
+// Fused levels per storage.  The 16-bit formats move 36 bytes per node update
+// and their single-step sweep is already faster than the fused one (which
+// spends VALU work on recomputed halos); they run one step per launch.
+template <int ST> struct FusedLevels { static constexpr int K = 6; };
+template <> struct FusedLevels<LB_F16S> { static constexpr int K = 1; };
+template <> struct FusedLevels<LB_BF16S> { static constexpr int K = 1; };
+
+// lane l <- lane l - 1 (wave_shr:1) and lane l <- lane l + 1 (wave_shl:1).
+// Lanes without a source keep their own value; they are outside the valid
+// region of the next level anyway.
+__device__ __forceinline__ float from_left(float v) {
+  const int b = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float from_right(float v) {
+  const int b = __float_as_int(v);
+  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x130, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double from_left(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x138, 0xF, 0xF, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double from_right(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_update_dpp(hi, hi, 0x130, 0xF, 0xF, false),
+                          __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xF, 0xF, false));
+}
+
+template <int K, int EQ, int COLL, int BC, int ST>
+__global__ __launch_bounds__(256) void fused_sweep_kernel(
+    const typename Storage<ST>::T* __restrict__ src, typename Storage<ST>::T* __restrict__ dst,
+    Geometry g, Coef64 c, int strips, int items) {
+  using S = Storage<ST>;
+  using R = typename S::R;
+  using Tt = typename S::T;
+  constexpr int W = 64 - 2 * K;
+  constexpr int H = kFusedRows;
+  constexpr int J = H + 2 * K;  // rows of level 0 read per wavefront
+  static_assert(J % 2 == 0, "the row loop runs in pairs");
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wave >= items) return;  // whole wavefronts leave together
+  const int strip = wave % strips, seg = wave / strips;
+  const int X0 = strip * W, Y0 = seg * H;
+  const int nx = g.nx, ny = g.ny;
+  const int64_t P = g.plane;
+  int col = (X0 - K + lane) % nx;
+  if (col < 0) col += nx;
+  const bool store_lane = lane >= K && lane < 64 - K && X0 - K + lane < nx;
+  const bool wall = BC == LB_BC_BOUNCEBACK && (col == 0 || col == nx - 1);
+  const Coeffs<R> k(c);
+  // Window of level lv: two row slots holding pops 0, 1, 2, 3, 5, 6 (pops 4,
+  // 7, 8 of a row are used as soon as it arrives).  Row j of a level lives in
+  // slot j % 2; with the row loop taken in pairs the slot roles are fixed at
+  // compile time and the window slides without register moves.
+  R Sl[K][2][6];
+  int row = (Y0 - K) % ny;
+  if (row < 0) row += ny;
+  Tt nb[2][9];  // level-0 rows: the one in use and the one in flight
+#pragma unroll
+  for (int i = 0; i < 9; ++i) nb[0][i] = src[i * P + (int64_t)row * nx + col];
+
+  auto one_row = [&](int j, auto PAR) {
+    constexpr int p = decltype(PAR)::value;  // j % 2
+    R C[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) C[i] = S::load(nb[p][i]);
+    if (j + 1 < J) {  // prefetch the next row of level 0
+      row = wrap_inc(row, ny);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) nb[1 - p][i] = src[i * P + (int64_t)row * nx + col];
+    }
+#pragma unroll
+    for (int lv = 0; lv < K; ++lv) {
+      const bool produce = j >= 2 * (lv + 1);  // level lv + 1 has its three source rows
+      R N[9];
+      if (produce) {
+        const R(&A)[6] = Sl[lv][p];      // row j - 2 (pops 2, 5, 6 used)
+        const R(&B)[6] = Sl[lv][1 - p];  // row j - 1 (pops 0, 1, 3 used)
+        N[0] = B[0];
+        N[1] = from_left(B[1]);
+        N[3] = from_right(B[3]);
+        N[2] = A[2];
+        N[5] = from_left(A[4]);
+        N[6] = from_right(A[5]);
+        N[4] = C[4];
+        N[7] = from_right(C[7]);
+        N[8] = from_left(C[8]);
+        if (wall) {
+          R r[9];
+          unroll<0, 9>([&](auto I) { r[I.value] = N[opp_of(I.value)]; });
+          unroll<0, 9>([&](auto I) { N[I.value] = r[I.value]; });
+        } else {
+          collide<EQ, COLL, S::shifted>(N, k);
+        }
+      }
+      Sl[lv][p][0] = C[0];
+      Sl[lv][p][1] = C[1];
+      Sl[lv][p][2] = C[2];
+      Sl[lv][p][3] = C[3];
+      Sl[lv][p][4] = C[5];
+      Sl[lv][p][5] = C[6];
+      if (!produce) break;  // deeper levels have no rows yet
+      if (lv + 1 == K) {
+        const int y = Y0 + j - 2 * K;
+        if (store_lane && y < ny) {
+#pragma unroll
+          for (int i = 0; i < 9; ++i)
+            __builtin_nontemporal_store(S::store(N[i]), dst + i * P + (int64_t)y * nx + col);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) C[i] = S::load(S::store(N[i]));
+      }
+    }
+  };
+  for (int j = 0; j < J; j += 2) {
+    one_row(j, IC<0>{});
+    one_row(j + 1, IC<1>{});
+  }
+}
+
 // ----------------------------------------------------------------- init --
 template <int EQ, int ST>
 __global__ __launch_bounds__(kThreads) void init_kernel(const double* __restrict__ rho,
@@ -212,7 +348,7 @@ __global__ __launch_bounds__(kThreads) void init_kernel(const double* __restrict
   }
   const Coeffs<double> k(c);
   double feq[9], deq[9];
-  equilibrium<EQ, S::shifted>(S::shifted ? r - c.rho0 : r, r, vx, vy, k, feq, deq);
+  equilibrium<EQ, S::shifted>(S::shifted ? r - c.rho0 : r, r, vx, vy, vx * vx, vy * vy, k, feq, deq);
   // f_i(x, 0) = f^eq_i(x) is stored as g_i(x - c_i).
   unroll<0, 9>([&](auto I) {
     constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
@@ -460,6 +596,42 @@ hipError_t launch_sweep(int eq, int coll, int bc, int st, const void* src, void*
         });
       });
     });
+  });
+}
+
+int fused_levels(int st) {
+  switch (st) {
+    case LB_F64: return FusedLevels<LB_F64>::K;
+    case LB_F32S: return FusedLevels<LB_F32S>::K;
+    case LB_F16S: return FusedLevels<LB_F16S>::K;
+    case LB_BF16S: return FusedLevels<LB_BF16S>::K;
+    default: return 1;
+  }
+}
+
+hipError_t launch_fused_sweep(int eq, int coll, int bc, int st, const void* src, void* dst,
+                              const Geometry& g, const Coef64& c, hipStream_t s) {
+  return with_storage(st, [&](auto ST) -> hipError_t {
+    using T = typename Storage<ST.value>::T;
+    constexpr int K = FusedLevels<ST.value>::K;
+    if constexpr (K < 2) {
+      return hipErrorInvalidValue;  // single-step storage: use launch_sweep
+    } else {
+    constexpr int W = 64 - 2 * K;
+    const int strips = (g.nx + W - 1) / W;
+    const int segs = (g.ny + kFusedRows - 1) / kFusedRows;
+    const int items = strips * segs;
+    const unsigned int nblocks = (unsigned int)((items + 3) / 4);
+    return with_eq(eq, [&](auto EQ) {
+      return with_coll(coll, [&](auto CO) {
+        return with_bc(bc, [&](auto BC) {
+          fused_sweep_kernel<K, EQ.value, CO.value, BC.value, ST.value><<<nblocks, 256, 0, s>>>(
+              static_cast<const T*>(src), static_cast<T*>(dst), g, c, strips, items);
+          return hipGetLastError();
+        });
+      });
+    });
+    }
   });
 }
 

@@ -27,6 +27,13 @@ constexpr int kDiagBlocks = 1024;
 hipError_t launch_sweep(int eq, int coll, int bc, int st, const void* src, void* dst,
                         const Geometry& g, const Coef64& c, hipStream_t s);
 
+// Time steps one fused launch advances for a storage format.
+int fused_levels(int st);
+
+// fused_levels(st) time steps in one launch: src -> dst.
+hipError_t launch_fused_sweep(int eq, int coll, int bc, int st, const void* src, void* dst,
+                              const Geometry& g, const Coef64& c, hipStream_t s);
+
 // g from fields (device FP64 [ny][nx] each); counts invalid input nodes
 // (non-finite value or rho <= 0) into *bad.
 hipError_t launch_init(int eq, int st, const double* rho, const double* ux, const double* uy,

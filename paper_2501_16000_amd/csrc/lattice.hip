@@ -112,6 +112,8 @@ lb_status validate(const lb_options* o) {
     return fail(nullptr, LB_EINVAL, "polynomial equilibrium needs theta = 1/3 (got %.17g)", o->theta);
   if (o->storage != LB_F64 && (!is_finite(o->rho0) || !(o->rho0 > 0.0)))
     return fail(nullptr, LB_EINVAL, "rho0 must be finite and > 0 for shifted storage");
+  if (o->fuse_steps != 0 && o->fuse_steps != 1)
+    return fail(nullptr, LB_EINVAL, "fuse_steps must be 0 or 1 (got %d)", o->fuse_steps);
   return LB_OK;
 }
 
@@ -169,6 +171,7 @@ void lb_options_init(lb_options* o) {
   o->use_stream = 0;
   o->device = -1;
   o->check_nonfinite = 0;
+  o->fuse_steps = 0;
 }
 
 lb_status lb_create(int nx, int ny, double tau, double theta, lb_equilibrium eq,
@@ -281,7 +284,18 @@ lb_status lb_step(lb_lattice* h, int64_t n) {
   if (n == 0) return LB_OK;
   DeviceScope ds(h->device);
   if (!ds.ok) return fail(h, LB_EDEVICE, "cannot select device %d", h->device);
-  for (int64_t k = 0; k < n; ++k) {
+  // Fused launches advance K steps each; the remainder runs one step per launch.
+  const int64_t K = h->opt.fuse_steps == 0 ? fused_levels(h->opt.storage) : 1;
+  int64_t left = n;
+  while (K > 1 && left >= K) {
+    HIP_TRY(h, launch_fused_sweep(h->opt.equilibrium, h->opt.collision, h->opt.boundary_x,
+                                  h->opt.storage, h->buf[h->cur], h->buf[1 - h->cur], h->geo,
+                                  h->coef, h->stream));
+    h->cur = 1 - h->cur;
+    h->t += K;
+    left -= K;
+  }
+  for (; left > 0; --left) {
     HIP_TRY(h, launch_sweep(h->opt.equilibrium, h->opt.collision, h->opt.boundary_x,
                             h->opt.storage, h->buf[h->cur], h->buf[1 - h->cur], h->geo, h->coef,
                             h->stream));

@@ -60,6 +60,7 @@ class lb_options(ctypes.Structure):
         ("use_stream", ctypes.c_int),
         ("device", ctypes.c_int),
         ("check_nonfinite", ctypes.c_int),
+        ("fuse_steps", ctypes.c_int),
     ]
 
 
@@ -139,6 +140,8 @@ class Lattice:
     Parameters mirror ``lb_options``; string names select the enums:
     equilibrium 'guided' | 'poly2', storage 'f64' | 'f32s' | 'f16s' | 'bf16s',
     collision 'oreg' | 'bgk', boundary_x 'periodic' | 'bounceback'.
+    ``fuse_steps`` 0 lets ``step`` fuse several time steps per launch, 1 runs
+    one sweep launch per step (identical results).
     ``stream`` is a HIP stream handle (int, 0 = the null stream) or a
     ``torch.cuda.Stream``; None lets the lattice create its own stream.
     """
@@ -146,7 +149,7 @@ class Lattice:
     def __init__(self, nx: int, ny: int, tau: float, theta: float = 1.0 / 3.0,
                  equilibrium: str = "guided", storage: str = "f64", collision: str = "oreg",
                  boundary_x: str = "periodic", rho0: float = 1.0, stream=None,
-                 device: int = -1, check_nonfinite: bool = False):
+                 device: int = -1, check_nonfinite: bool = False, fuse_steps: int = 0):
         o = lb_options()
         lb_options_init(ctypes.byref(o))
         o.nx, o.ny, o.tau, o.theta = int(nx), int(ny), float(tau), float(theta)
@@ -162,6 +165,7 @@ class Lattice:
             o.use_stream = 1
         o.device = int(device)
         o.check_nonfinite = int(bool(check_nonfinite))
+        o.fuse_steps = int(fuse_steps)
         h = _H()
         check(lb_create_ex(ctypes.byref(o), ctypes.byref(h)))
         self._h = h

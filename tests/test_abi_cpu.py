@@ -50,9 +50,9 @@ def test_options_defaults_and_struct_layout():
     assert o.equilibrium == m.LB_EQ_GUIDED and o.storage == m.LB_F64
     assert o.collision == m.LB_COLL_OREG and o.boundary_x == m.LB_BC_PERIODIC
     assert o.rho0 == 1.0 and o.device == -1 and not o.stream and o.check_nonfinite == 0
-    assert o.use_stream == 0
-    # C layout of lb_options: 2 ints, 2 doubles, 4 enums, double, pointer, 3 ints (+pad)
-    assert ctypes.sizeof(m.lb_options) == 4 * 2 + 8 * 2 + 4 * 4 + 8 + 8 + 4 * 3 + 4
+    assert o.use_stream == 0 and o.fuse_steps == 0
+    # C layout of lb_options: 2 ints, 2 doubles, 4 enums, double, pointer, 4 ints
+    assert ctypes.sizeof(m.lb_options) == 4 * 2 + 8 * 2 + 4 * 4 + 8 + 8 + 4 * 4
 
 
 INVALID = [
@@ -60,7 +60,8 @@ INVALID = [
     dict(tau=math.inf), dict(theta=0.0), dict(theta=1.0), dict(theta=math.nan),
     dict(equilibrium=1, theta=0.35), dict(equilibrium=7), dict(storage=9), dict(collision=3),
     dict(boundary_x=5), dict(storage=1, rho0=0.0), dict(storage=2, rho0=-1.0),
-    dict(storage=3, rho0=math.inf), dict(nx=1, ny=20_000_000),
+    dict(storage=3, rho0=math.inf), dict(nx=1, ny=20_000_000), dict(fuse_steps=2),
+    dict(fuse_steps=-1),
 ]
 
 

@@ -302,3 +302,38 @@ def test_device_init_and_moments_with_torch():
     np.testing.assert_array_equal(got, host)
     ref = oracle.moments(oracle.run(oracle.init("guided", theta, rho, ux, uy), 30, tau, theta))
     assert np.max(np.abs(got - ref)) < 1e-13
+
+
+FUSED_CASES = [
+    # (nx, ny, eq, theta, tau, collision, bc, storage)
+    (300, 77, "guided", 1 / 3, 0.8, "oreg", "periodic", "f64"),
+    (64, 64, "guided", 0.35, 0.51, "oreg", "periodic", "f64"),
+    (37, 5, "poly2", 1 / 3, 0.6, "oreg", "periodic", "f64"),
+    (1, 200, "guided", 1 / 3, 0.53, "oreg", "periodic", "f64"),
+    (800, 1, "guided", 0.4, 0.6, "oreg", "bounceback", "f64"),
+    (53, 71, "guided", 1 / 3, 0.9, "bgk", "periodic", "f64"),
+    (130, 3, "poly2", 1 / 3, 0.7, "bgk", "bounceback", "f64"),
+    (513, 130, "guided", 1 / 3, 0.6, "oreg", "periodic", "f32s"),
+    (200, 40, "poly2", 1 / 3, 0.7, "oreg", "periodic", "f16s"),
+    (97, 33, "guided", 0.35, 0.8, "oreg", "bounceback", "bf16s"),
+]
+
+
+@pytest.mark.parametrize("nx,ny,eq,theta,tau,coll,bc,storage", FUSED_CASES)
+def test_fused_steps_equal_single_steps(nx, ny, eq, theta, tau, coll, bc, storage):
+    """lb_step fuses several time steps per launch by default; the result is
+    bit for bit that of one sweep launch per step (fuse_steps = 1)."""
+    oreg = lib()
+    say(f"[fused] {nx}x{ny} {eq} {coll} {bc} {storage}")
+    f0 = random_populations(eq, theta, ny, nx, seed=7 * nx + ny)
+    out = []
+    for fuse in (0, 1):
+        with oreg.Lattice(nx, ny, tau, theta, equilibrium=eq, collision=coll, boundary_x=bc,
+                          storage=storage, rho0=1.0, fuse_steps=fuse) as L:
+            L.set_populations(f0)
+            L.step(37)
+            out.append(L.populations())
+    np.testing.assert_array_equal(out[0], out[1])
+    if storage == "f64":
+        ref = oracle.run(f0, 37, tau, theta, eq, collision=coll, bc_x=bc)
+        assert rel_err(out[0], ref) <= RTOL

@@ -99,9 +99,12 @@ typedef struct lb_options {
   int device;                 /* HIP device ordinal; -1: current device         */
   int check_nonfinite;        /* nonzero: lb_step scans for NaN/Inf afterwards  */
   int fuse_steps;             /* 0: lb_step advances several time steps per
-                                 launch where it can (register-resident
+                                 launch when the lattice is large enough for
+                                 that to be faster (register-resident
                                  multi-step sweep; same result bit for bit);
-                                 1: one sweep launch per time step             */
+                                 1: one sweep launch per time step;
+                                 2: fused launches whenever the storage has
+                                 them (F64, F32S), whatever the size           */
 } lb_options;
 
 /* Defaults: 0 x 0, tau 1, theta 1/3, guided, LB_F64, OReg, periodic, rho0 1,
@@ -112,7 +115,7 @@ void lb_options_init(lb_options* opt);
 /* FP64 periodic OReg lattice on the current device with its own stream.
    LB_EINVAL: nx or ny < 1, too large, tau or theta not finite, tau <= 1/2,
    guided with theta outside (0, 1), polynomial with |theta - 1/3| > 1e-12,
-   unknown enum, fuse_steps not 0 or 1, out == NULL.  LB_ENOMEM / LB_EDEVICE
+   unknown enum, fuse_steps not 0, 1 or 2, out == NULL.  LB_ENOMEM / LB_EDEVICE
    from HIP. */
 lb_status lb_create(int nx, int ny, double tau, double theta, lb_equilibrium eq,
                     lb_lattice** out);
@@ -197,12 +200,13 @@ const char* lb_last_error(const lb_lattice* h);
  * admits a request at once when a slot and arena space are free (its
  * footprint is 2 * 9 * sizeof(storage) + 24 bytes per node) and returns
  * LB_EAGAIN otherwise, so the caller keeps the queue and retries as lattices
- * retire.  lb_server_step advances every resident lattice by one time step per
- * iteration with a single batched launch that covers all of them (each lattice
- * runs the same per-node update as lb_step, Eqs. (6), (7) with the server's
- * equilibrium and storage and the request's tau), and retires each lattice
- * after its requested number of steps: its moments are gathered and copied to
- * pinned host memory asynchronously.  lb_server_poll reports finished results,
+ * retire.  lb_server_step issues batched launches; one launch covers every
+ * resident lattice and advances each by up to K time steps (K = 6 for LB_F64
+ * and LB_F32S storage, 1 for the 16-bit formats; fewer in a lattice's last
+ * launch), running the same per-node update as lb_step (Eqs. (6), (7) with the
+ * server's equilibrium and storage and the request's tau).  Each lattice is
+ * retired after its requested number of steps: its moments are gathered and
+ * copied to pinned host memory asynchronously.  lb_server_poll reports finished results,
  * lb_server_fetch hands their moments to the caller.  A result does not depend
  * on which other lattices shared the launches: the per-node arithmetic is that
  * of a lattice running alone.
@@ -244,8 +248,8 @@ typedef struct lb_server_stats {
   int retiring;               /* finished, moments in flight to the host       */
   int ready;                  /* results waiting for lb_server_fetch           */
   int64_t device_bytes_used;  /* arena bytes held                              */
-  int64_t launches;           /* batched sweeps launched                       */
-  int64_t node_updates;       /* sum over launches of the nodes they updated   */
+  int64_t launches;           /* batched launches issued                       */
+  int64_t node_updates;       /* node updates done (nodes x steps)             */
   double clock;               /* server clock now (seconds)                    */
 } lb_server_stats;
 
@@ -263,7 +267,7 @@ lb_status lb_server_create(const lb_server_options* opt, lb_server** out);
    larger than the whole arena. */
 lb_status lb_server_submit(lb_server* s, const lb_request* req);
 
-/* Run up to n batched steps (fewer if no lattice is resident); retires
+/* Issue up to n batched launches (fewer if no lattice is resident); retires
    lattices as they finish.  Asynchronous: returns once the launches are
    enqueued. */
 lb_status lb_server_step(lb_server* s, int64_t n);

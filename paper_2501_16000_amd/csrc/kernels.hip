@@ -326,6 +326,98 @@ __global__ __launch_bounds__(256) void fused_sweep_kernel(
   }
 }
 
+// Batched form of fused_sweep_kernel for the server: each wavefront takes one
+// work item (lattice, column strip, row block) of a descriptor table and runs
+// the same pipeline with that lattice's own step count kl <= KMAX and row
+// block height.  Strips are KMAX-wide at every kl, so the item layout of a
+// lattice does not change when its last launch has fewer steps.
+template <int KMAX, int EQ, int ST>
+__global__ __launch_bounds__(256) void batched_fused_kernel(const LatticeDesc* __restrict__ d,
+                                                            const int* __restrict__ map,
+                                                            int64_t items, int64_t T) {
+  using S = Storage<ST>;
+  using R = typename S::R;
+  using Tt = typename S::T;
+  constexpr int W = 64 - 2 * KMAX;
+  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (item >= items) return;  // whole wavefronts leave together
+  const LatticeDesc& L = d[map[item]];
+  const int local = (int)(item - L.tile_begin);
+  const int strip = local % L.strips, seg = local / L.strips;
+  const int kl = L.kl, H = L.rows;
+  const int X0 = strip * W, Y0 = seg * H;
+  const int nx = L.nx, ny = L.ny;
+  const int64_t P = L.plane;
+  const int64_t t = T - L.admit_T;
+  const Tt* __restrict__ src = static_cast<const Tt*>(L.buf[t & 1]);
+  Tt* __restrict__ dst = static_cast<Tt*>(L.buf[(t + 1) & 1]);
+  int col = (X0 - KMAX + lane) % nx;
+  if (col < 0) col += nx;
+  const bool store_lane = lane >= KMAX && lane < 64 - KMAX && X0 - KMAX + lane < nx;
+  const Coeffs<R> k(L.coef);
+  R Sl[KMAX][2][6];
+  int row = (Y0 - kl) % ny;
+  if (row < 0) row += ny;
+  const int J = H + 2 * kl;  // even: H is even
+  Tt nb[2][9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) nb[0][i] = src[i * P + (int64_t)row * nx + col];
+
+  auto one_row = [&](int j, auto PAR) {
+    constexpr int p = decltype(PAR)::value;
+    R C[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) C[i] = S::load(nb[p][i]);
+    if (j + 1 < J) {
+      row = wrap_inc(row, ny);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) nb[1 - p][i] = src[i * P + (int64_t)row * nx + col];
+    }
+#pragma unroll
+    for (int lv = 0; lv < KMAX; ++lv) {
+      const bool produce = j >= 2 * (lv + 1);
+      R N[9];
+      if (produce) {
+        const R(&A)[6] = Sl[lv][p];
+        const R(&B)[6] = Sl[lv][1 - p];
+        N[0] = B[0];
+        N[1] = from_left(B[1]);
+        N[3] = from_right(B[3]);
+        N[2] = A[2];
+        N[5] = from_left(A[4]);
+        N[6] = from_right(A[5]);
+        N[4] = C[4];
+        N[7] = from_right(C[7]);
+        N[8] = from_left(C[8]);
+        collide<EQ, LB_COLL_OREG, S::shifted>(N, k);
+      }
+      Sl[lv][p][0] = C[0];
+      Sl[lv][p][1] = C[1];
+      Sl[lv][p][2] = C[2];
+      Sl[lv][p][3] = C[3];
+      Sl[lv][p][4] = C[5];
+      Sl[lv][p][5] = C[6];
+      if (!produce) break;
+      if (lv + 1 == kl) {
+        const int y = Y0 + j - 2 * kl;
+        if (store_lane && y < ny && y < Y0 + H) {
+#pragma unroll
+          for (int i = 0; i < 9; ++i)
+            __builtin_nontemporal_store(S::store(N[i]), dst + i * P + (int64_t)y * nx + col);
+        }
+        break;
+      }
+#pragma unroll
+      for (int i = 0; i < 9; ++i) C[i] = S::load(S::store(N[i]));
+    }
+  };
+  for (int j = 0; j < J; j += 2) {
+    one_row(j, IC<0>{});
+    one_row(j + 1, IC<1>{});
+  }
+}
+
 // ----------------------------------------------------------------- init --
 template <int EQ, int ST>
 __global__ __launch_bounds__(kThreads) void init_kernel(const double* __restrict__ rho,
@@ -707,6 +799,38 @@ hipError_t launch_batched_sweep(int eq, int st, const LatticeDesc* d, const int*
           d, tile_map, T);
       return hipGetLastError();
     });
+  });
+}
+
+int fused_strip_width(int st) { return 64 - 2 * fused_levels(st); }
+
+bool fused_worthwhile(int st, int nx, int ny) {
+  const int K = fused_levels(st);
+  if (K < 2 || ny < kFusedRows) return false;
+  const int64_t items = (int64_t)((nx + (64 - 2 * K) - 1) / (64 - 2 * K)) *
+                        ((ny + kFusedRows - 1) / kFusedRows);
+  // A wavefront's row pipeline takes about 0.1 ms, so the fused sweep needs
+  // enough wavefronts to fill the GPU before it beats the single-step sweep
+  // (measured crossovers on MI355X: about 900^2 nodes for F64, 1300^2 for
+  // F32S, where the single-step sweep runs from the 256 MB last-level cache).
+  const int64_t min_items = (st == LB_F64) ? 300 : 600;
+  return items >= min_items;
+}
+
+hipError_t launch_batched_fused(int eq, int st, const LatticeDesc* d, const int* item_map,
+                                int64_t items, int64_t T, hipStream_t s) {
+  if (items <= 0) return hipSuccess;
+  return with_storage(st, [&](auto ST) -> hipError_t {
+    constexpr int K = FusedLevels<ST.value>::K;
+    if constexpr (K < 2) {
+      return hipErrorInvalidValue;
+    } else {
+      return with_eq(eq, [&](auto EQ) {
+        batched_fused_kernel<K, EQ.value, ST.value>
+            <<<(unsigned int)((items + 3) / 4), 256, 0, s>>>(d, item_map, items, T);
+        return hipGetLastError();
+      });
+    }
   });
 }
 

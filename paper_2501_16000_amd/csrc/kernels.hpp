@@ -30,6 +30,9 @@ hipError_t launch_sweep(int eq, int coll, int bc, int st, const void* src, void*
 // Time steps one fused launch advances for a storage format.
 int fused_levels(int st);
 
+// Whether fused launches beat single-step launches for this lattice size.
+bool fused_worthwhile(int st, int nx, int ny);
+
 // fused_levels(st) time steps in one launch: src -> dst.
 hipError_t launch_fused_sweep(int eq, int coll, int bc, int st, const void* src, void* dst,
                               const Geometry& g, const Coef64& c, hipStream_t s);
@@ -69,8 +72,12 @@ struct LatticeDesc {
   double* fields;      // 3 * plane FP64: initial fields, later the result moments
   int nx, ny;
   int64_t plane;       // nx * ny
-  int64_t admit_T;     // server step counter when admitted (local time = T - admit_T)
-  int64_t tile_begin;  // first tile of this lattice in the batched launch
+  int64_t admit_T;     // server launch counter at admission; the state is in
+                       // buf[(T - admit_T) % 2] before launch T
+  int64_t tile_begin;  // first tile (single-step) or work item (fused) of this lattice
+  int kl;              // fused launches: time steps this launch advances the lattice
+  int rows;            // fused launches: output rows per work item
+  int strips;          // fused launches: column strips
   Coef64 coef;
 };
 
@@ -85,5 +92,12 @@ hipError_t launch_tile_map(const LatticeDesc* d, int n, int* tile_map, int64_t t
 // One time step of every lattice in d[0..n): tiles workgroups, global step T.
 hipError_t launch_batched_sweep(int eq, int st, const LatticeDesc* d, const int* tile_map,
                                 int64_t tiles, int64_t T, hipStream_t s);
+
+// Fused batched launches: up to fused_levels(st) steps per lattice per launch
+// (d[i].kl each), one wavefront per work item (a column strip x a row block).
+// Column strip width of the fused sweep for storage st.
+int fused_strip_width(int st);
+hipError_t launch_batched_fused(int eq, int st, const LatticeDesc* d, const int* item_map,
+                                int64_t items, int64_t T, hipStream_t s);
 
 }  // namespace oreg

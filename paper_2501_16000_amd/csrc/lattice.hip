@@ -112,8 +112,8 @@ lb_status validate(const lb_options* o) {
     return fail(nullptr, LB_EINVAL, "polynomial equilibrium needs theta = 1/3 (got %.17g)", o->theta);
   if (o->storage != LB_F64 && (!is_finite(o->rho0) || !(o->rho0 > 0.0)))
     return fail(nullptr, LB_EINVAL, "rho0 must be finite and > 0 for shifted storage");
-  if (o->fuse_steps != 0 && o->fuse_steps != 1)
-    return fail(nullptr, LB_EINVAL, "fuse_steps must be 0 or 1 (got %d)", o->fuse_steps);
+  if (o->fuse_steps < 0 || o->fuse_steps > 2)
+    return fail(nullptr, LB_EINVAL, "fuse_steps must be 0, 1 or 2 (got %d)", o->fuse_steps);
   return LB_OK;
 }
 
@@ -285,7 +285,10 @@ lb_status lb_step(lb_lattice* h, int64_t n) {
   DeviceScope ds(h->device);
   if (!ds.ok) return fail(h, LB_EDEVICE, "cannot select device %d", h->device);
   // Fused launches advance K steps each; the remainder runs one step per launch.
-  const int64_t K = h->opt.fuse_steps == 0 ? fused_levels(h->opt.storage) : 1;
+  const bool fuse =
+      h->opt.fuse_steps == 2 ||
+      (h->opt.fuse_steps == 0 && fused_worthwhile(h->opt.storage, h->geo.nx, h->geo.ny));
+  const int64_t K = fuse ? fused_levels(h->opt.storage) : 1;
   int64_t left = n;
   while (K > 1 && left >= K) {
     HIP_TRY(h, launch_fused_sweep(h->opt.equilibrium, h->opt.collision, h->opt.boundary_x,

@@ -20,6 +20,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <deque>
 #include <map>
 #include <new>
@@ -103,6 +104,9 @@ struct ServedLattice {
   hipEvent_t upload_done = nullptr;
   bool upload_pending = false;
   int64_t admit_T;
+  int64_t done = 0;     // time steps run
+  int64_t nlaunch = 0;  // batched launches taken part in (state in buf[nlaunch % 2])
+  int kl = 1;           // steps of the next launch
   double t_submit;
   // retirement
   size_t out_off = 0, out_bytes = 0;  // pinned result block
@@ -193,6 +197,10 @@ LatticeDesc describe(const lb_server* s, const ServedLattice* L) {
   d.ny = L->ny;
   d.plane = cells;
   d.admit_T = L->admit_T;
+  const int W = fused_strip_width(s->opt.storage);
+  d.kl = L->kl;
+  d.rows = L->ny < 64 ? L->ny + (L->ny & 1) : 64;  // even, so rows + 2 kl is even
+  d.strips = (L->nx + W - 1) / W;
   d.coef = s->base;
   d.coef.kappa0 = (1.0 - 1.0 / L->tau) / (2.0 * s->base.theta * s->base.theta);
   d.coef.omega = 1.0 / L->tau;
@@ -239,10 +247,14 @@ lb_status upload_descriptors(lb_server* s) {
   int64_t tiles = 0;
   const int slot = s->desc_slot;
   STRY(s, hipEventSynchronize(s->desc_done[slot]));  // staging slot free again
+  const bool fused = fused_levels(s->opt.storage) > 1;
   for (int i = 0; i < n; ++i) {
     LatticeDesc d = describe(s, s->active[i]);
     d.tile_begin = tiles;
-    tiles += (d.plane + kBatchTile - 1) / kBatchTile;
+    if (fused)
+      tiles += (int64_t)d.strips * ((d.ny + d.rows - 1) / d.rows);
+    else
+      tiles += (d.plane + kBatchTile - 1) / kBatchTile;
     s->h_desc[slot][i] = d;
   }
   if (tiles > s->map_capacity) {
@@ -275,8 +287,8 @@ lb_status retire(lb_server* s, ServedLattice* L) {
   const size_t bytes = 3 * (size_t)cells * sizeof(double);
   const bool pinned = s->pin_out_arena.alloc(bytes, &L->out_off);
   L->out_bytes = bytes;
-  const int64_t t = L->steps;  // local time after the last step
-  STRY(s, launch_moments(s->opt.storage, d.buf[t & 1], d.fields, g, d.coef, s->compute));
+  STRY(s, launch_moments(s->opt.storage, d.buf[L->nlaunch & 1], d.fields, g, d.coef,
+                         s->compute));
   hipEvent_t gathered;
   STRY(s, hipEventCreateWithFlags(&gathered, hipEventDisableTiming));
   STRY(s, hipEventRecord(gathered, s->compute));
@@ -480,20 +492,38 @@ lb_status lb_server_step(lb_server* s, int64_t n) {
   if (n < 0) return fail(s, LB_EINVAL, "n %lld", (long long)n);
   DeviceScope ds(s->device);
   if (!ds.ok) return fail(s, LB_EDEVICE, "cannot select device %d", s->device);
+  const int K = fused_levels(s->opt.storage);
   for (int64_t k = 0; k < n && !s->active.empty(); ++k) {
+    if (K > 1) {
+      // a lattice's last launch may advance it fewer than K steps
+      for (ServedLattice* L : s->active) {
+        const int want = (int)std::min<int64_t>(K, L->steps - L->done);
+        if (want != L->kl) {
+          L->kl = want;
+          s->dirty = true;
+        }
+      }
+    }
     if (s->dirty) {
       lb_status st = upload_descriptors(s);
       if (st != LB_OK) return st;
     }
-    STRY(s, launch_batched_sweep(s->opt.equilibrium, s->opt.storage, s->d_desc, s->d_map,
-                                 s->tiles, s->T, s->compute));
+    if (K > 1)
+      STRY(s, launch_batched_fused(s->opt.equilibrium, s->opt.storage, s->d_desc, s->d_map,
+                                   s->tiles, s->T, s->compute));
+    else
+      STRY(s, launch_batched_sweep(s->opt.equilibrium, s->opt.storage, s->d_desc, s->d_map,
+                                   s->tiles, s->T, s->compute));
     s->T += 1;
     s->launches += 1;
     // retire lattices that have run their steps
     for (size_t i = 0; i < s->active.size();) {
       ServedLattice* L = s->active[i];
-      s->node_updates += (int64_t)L->nx * L->ny;
-      if (s->T - L->admit_T >= L->steps) {
+      const int adv = K > 1 ? L->kl : 1;
+      L->done += adv;
+      L->nlaunch += 1;
+      s->node_updates += (int64_t)L->nx * L->ny * adv;
+      if (L->done >= L->steps) {
         lb_status st = retire(s, L);
         if (st != LB_OK) return st;
         s->active.erase(s->active.begin() + (long)i);

@@ -140,8 +140,9 @@ class Lattice:
     Parameters mirror ``lb_options``; string names select the enums:
     equilibrium 'guided' | 'poly2', storage 'f64' | 'f32s' | 'f16s' | 'bf16s',
     collision 'oreg' | 'bgk', boundary_x 'periodic' | 'bounceback'.
-    ``fuse_steps`` 0 lets ``step`` fuse several time steps per launch, 1 runs
-    one sweep launch per step (identical results).
+    ``fuse_steps`` 0 lets ``step`` fuse several time steps per launch when the
+    lattice is large enough, 1 runs one sweep launch per step, 2 fuses at any
+    size (identical results in every case).
     ``stream`` is a HIP stream handle (int, 0 = the null stream) or a
     ``torch.cuda.Stream``; None lets the lattice create its own stream.
     """

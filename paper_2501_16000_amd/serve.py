@@ -115,6 +115,8 @@ class Server:
         return True
 
     def step(self, n: int = 1) -> None:
+        """Issue up to n batched launches (each advances every resident lattice
+        by up to 6 time steps for F64/F32S storage, 1 for 16-bit storage)."""
         self._check(lb_server_step(self._h, int(n)))
 
     def poll(self):

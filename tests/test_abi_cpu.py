@@ -60,7 +60,7 @@ INVALID = [
     dict(tau=math.inf), dict(theta=0.0), dict(theta=1.0), dict(theta=math.nan),
     dict(equilibrium=1, theta=0.35), dict(equilibrium=7), dict(storage=9), dict(collision=3),
     dict(boundary_x=5), dict(storage=1, rho0=0.0), dict(storage=2, rho0=-1.0),
-    dict(storage=3, rho0=math.inf), dict(nx=1, ny=20_000_000), dict(fuse_steps=2),
+    dict(storage=3, rho0=math.inf), dict(nx=1, ny=20_000_000), dict(fuse_steps=3),
     dict(fuse_steps=-1),
 ]
 

@@ -321,13 +321,13 @@ FUSED_CASES = [
 
 @pytest.mark.parametrize("nx,ny,eq,theta,tau,coll,bc,storage", FUSED_CASES)
 def test_fused_steps_equal_single_steps(nx, ny, eq, theta, tau, coll, bc, storage):
-    """lb_step fuses several time steps per launch by default; the result is
-    bit for bit that of one sweep launch per step (fuse_steps = 1)."""
+    """Fused launches (fuse_steps = 2 forces them at any size) give bit for
+    bit the result of one sweep launch per step (fuse_steps = 1)."""
     oreg = lib()
     say(f"[fused] {nx}x{ny} {eq} {coll} {bc} {storage}")
     f0 = random_populations(eq, theta, ny, nx, seed=7 * nx + ny)
     out = []
-    for fuse in (0, 1):
+    for fuse in (2, 1):
         with oreg.Lattice(nx, ny, tau, theta, equilibrium=eq, collision=coll, boundary_x=bc,
                           storage=storage, rho0=1.0, fuse_steps=fuse) as L:
             L.set_populations(f0)

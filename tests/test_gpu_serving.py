@@ -175,3 +175,22 @@ def test_invalid_requests():
         with pytest.raises(oreg.LBError) as e:
             srv.submit(1, *big, 0.8, 5)   # larger than the whole arena
         assert e.value.status == oreg.LB_EINVAL
+
+
+@pytest.mark.parametrize("storage", ["f64", "f16s"])
+def test_other_storages_equal_single_lattice_path(storage):
+    """F64 serving uses fused launches, 16-bit storage single-step launches; both
+    equal lb_step on one lattice bit for bit, also when a lattice's steps are
+    not a multiple of the fused step count."""
+    oreg, serve = mods()
+    reqs = [workloads.ServingRequest(0, 0.0, 40, 0.7, 0.03, 31),
+            workloads.ServingRequest(1, 0.0, 70, 0.9, 0.02, 12),
+            workloads.ServingRequest(2, 0.0, 17, 0.55, 0.04, 5)]
+    say(f"[serve] {storage} mix vs lb_step")
+    with serve.Server(memory_budget=1 << 28, storage=storage) as srv:
+        got = serve_all(srv, reqs, steps_per_call=2)
+    for r in reqs:
+        with oreg.Lattice(r.n, r.n, r.tau, storage=storage) as L:
+            L.init(*workloads.shear_wave(r.n, r.u0))
+            L.step(r.steps)
+            np.testing.assert_array_equal(got[r.rid], L.moments())

@@ -432,6 +432,51 @@ def test_shocktube_plateau_matches_riemann_solution():
     assert abs(jump - x_shock) < 3
 
 
+def isothermal_riemann_density(x, t, rl, rr, cs, x0):
+    """Exact density of the isothermal Euler Riemann problem at rest: left
+    rarefaction, right shock, diaphragm at x0."""
+    rs, us = isothermal_riemann_plateau(rl, rr, cs)
+    s = rs * us / (rs - rr)
+    xi = (x - x0) / t
+    return np.where(xi < -cs, rl, np.where(xi < us - cs, rl * np.exp(-(xi + cs) / cs),
+                                           np.where(xi < s, rs, rr)))
+
+
+def walled_shocktube(collision, theta, nu, nx=800, steps=500, rl=1.5, rr=0.75):
+    """The walled shocktube of Sec. IV: full-way bounce-back wall columns, guided
+    equilibrium, density step at the middle (the ratio is not stated in the
+    paper; 2 is used).  Returns (accuracy, total variation of rho, rho)."""
+    tau = nu / theta + 0.5
+    x = np.arange(nx)
+    rho = np.where(x < nx // 2, rl, rr)[None, :].astype(float)
+    f = oracle.run(oracle.init("guided", theta, rho, 0 * rho, 0 * rho), steps, tau, theta,
+                   collision=collision, bc_x="bounceback")
+    r = oracle.moments(f)[0, 0]
+    ref = isothermal_riemann_density(x.astype(float), steps, rl, rr, math.sqrt(theta),
+                                     (nx - 1) / 2)
+    fl = slice(1, nx - 1)
+    acc = 1 - np.linalg.norm(r[fl] - ref[fl]) / np.linalg.norm(ref[fl])
+    return acc, np.abs(np.diff(r[fl])).sum(), r
+
+
+@pytest.mark.parametrize("theta,nu,paper", [(0.35, 1e-5, 0.9888), (0.4, 1e-9, 0.9820)])
+def test_walled_shocktube_accuracy_sec4(theta, nu, paper):
+    """Sec. IV: on 800 x 1 with bounce-back walls after 500 steps OReg captures the
+    density with about 98.88 % (theta = 0.35, nu = 1e-5) and 98.20 % (theta = 0.4,
+    nu = 1e-9) accuracy and no oscillations, lattice BGK with large ones.  With a
+    density ratio of 2 the oracle gives 99.18 % and 98.46 %."""
+    acc, tv, _ = walled_shocktube("oreg", theta, nu)
+    acc_bgk, tv_bgk, _ = walled_shocktube("bgk", theta, nu)
+    assert abs(acc - paper) < 5e-3
+    assert tv < 0.755          # monotone profile: total variation of the exact one is 0.75
+    assert tv_bgk > 10 * tv    # BGK oscillates
+    assert acc_bgk < acc - 0.03
+    # halved and doubled grids give similar accuracy (grid independence)
+    for nx, steps in ((400, 250), (1600, 1000)):
+        a, t, _ = walled_shocktube("oreg", theta, nu, nx, steps)
+        assert abs(a - acc) < 5e-3 and t < 0.755
+
+
 def test_bgk_conserves_mass_and_momentum():
     """Eq. (1): f^neq has zero mass and momentum because f^eq matches them (Eq. 2a)."""
     f0 = perturbed_state("guided", 0.35, 7, 9, 40)

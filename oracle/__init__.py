@@ -37,10 +37,13 @@ _BC = {"periodic": BC_PERIODIC, "bounceback": BC_BOUNCEBACK}
 
 
 def build() -> str:
-    """Compile the oracle with gcc (-O2, no fast-math, OpenMP)."""
+    """Compile the oracles with gcc (-O2, no fast-math, OpenMP): this D2Q9 one
+    and the D3Q27 one of ``oracle.d3q27``."""
     cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared",
            "-fopenmp", "-o", _LIB, _SRC, "-lm"]
     subprocess.run(cmd, check=True, cwd=_HERE)
+    from . import d3q27
+    d3q27.build()
     return _LIB
 
 

@@ -20,6 +20,9 @@ Workloads (the paper's benchmarks of Sec. IV, restated on periodic grids):
   with 8 x 8 Fourier modes and random phases (numpy PCG64, seeded), scaled to
   a given maximum speed.
 * ``serving_requests``: the request stream of the serving benchmark.
+* ``shear_wave3``: the 3D shear wave of the D3Q27 lattice, fronts normal to
+  the body diagonal: phase ``s = (x + y + z)/N``, ``|k|^2 = 3 (2 pi / N)^2``,
+  velocity along ``(1, -1, 0)/sqrt(2)``; 3D fields are ``[nz, ny, nx]``.
 """
 from __future__ import annotations
 
@@ -30,6 +33,7 @@ import numpy as np
 
 __all__ = [
     "shear_wave", "shear_wave_k2", "paper_shear_wave", "shocktube",
+    "shear_wave3", "shear_wave3_k2", "shear_wave3_projection",
     "smooth_random_velocity", "noise", "ServingRequest", "serving_requests",
 ]
 
@@ -63,6 +67,39 @@ def shear_wave_projection(n: int, mode: int = 1):
     x, y = _grid(n, n)
     s = mode * (2.0 * x + y) / n
     return np.array([-1.0, 2.0]) / math.sqrt(5.0), np.exp(-2j * np.pi * s)
+
+
+def _grid3(nx: int, ny: int, nz: int):
+    z, y, x = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                          np.arange(nx, dtype=np.float64), indexing="ij")
+    return x, y, z
+
+
+_E3 = np.array([1.0, -1.0, 0.0]) / math.sqrt(2.0)
+
+
+def shear_wave3(n: int, u0: float, rho: float = 1.0, nz: int | None = None):
+    """Shear wave on an ``n x n x nz`` periodic box (``nz = n`` by default),
+    wave vector ``(2 pi / n) (1, 1, 1)`` when ``nz = n``; returns
+    ``(rho, ux, uy, uz)``, each ``[nz, n, n]`` float64.  With ``nz != n`` the
+    phase is ``(x + y)/n + z/nz`` (still periodic)."""
+    nz = n if nz is None else nz
+    x, y, z = _grid3(n, n, nz)
+    s = (x + y) / n + z / nz
+    amp = u0 * np.sin(2.0 * np.pi * s)
+    return (np.full(x.shape, float(rho)), amp * _E3[0], amp * _E3[1], amp * _E3[2])
+
+
+def shear_wave3_k2(n: int, nz: int | None = None) -> float:
+    nz = n if nz is None else nz
+    return 2.0 * (2.0 * math.pi / n) ** 2 + (2.0 * math.pi / nz) ** 2
+
+
+def shear_wave3_projection(n: int, nz: int | None = None):
+    """Unit vector e_perp and the phase exp(-2 pi i s) of ``shear_wave3``."""
+    nz = n if nz is None else nz
+    x, y, z = _grid3(n, n, nz)
+    return _E3, np.exp(-2j * np.pi * ((x + y) / n + z / nz))
 
 
 def paper_shear_wave(ly: int, a0: float, ma: float, theta: float, rotated: bool, lx: int = 1):

@@ -1,8 +1,9 @@
 """MI355X (gfx950) implementation of the Onsager-regularized lattice Boltzmann
-sweep on the D2Q9 lattice (arXiv 2501.16000).
+sweep on the D2Q9 lattice, and its D3Q27 extension (arXiv 2501.16000).
 
 Submodules:
   ``oreg``       ctypes binding of ``liboreg.so`` (the C ABI of include/oreg.h);
+  ``oreg3``      the D3Q27 entry points (include/oreg3.h);
   ``serve``      continuous-batching serving of many independent lattices;
   ``workloads``  seeded synthetic initial fields and request streams;
   ``build``      in-tree hipcc build of ``liboreg.so``.
@@ -12,7 +13,7 @@ machine where the library has not been built yet.
 """
 import importlib
 
-__all__ = ["oreg", "workloads", "build", "serve"]
+__all__ = ["oreg", "oreg3", "workloads", "build", "serve"]
 
 
 def __getattr__(name):

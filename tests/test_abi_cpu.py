@@ -1,7 +1,8 @@
 """Host-side checks of the C ABI (no kernel launches): the library loads,
-exports every entry point that include/oreg.h declares, and validates its
-arguments before it touches a device."""
+exports every entry point that include/oreg.h and include/oreg3.h declare,
+and validates its arguments before it touches a device."""
 import ctypes
+import glob
 import math
 import os
 import re
@@ -10,7 +11,7 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "oreg.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def oreg():
@@ -19,9 +20,11 @@ def oreg():
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lb_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for path in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(path).read(), flags=re.S)
+        names |= set(re.findall(r"\b(lb3?_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_header_declares_the_boundary():
@@ -34,11 +37,11 @@ def test_library_exports_every_declared_symbol():
     m = oreg()
     out = subprocess.run(["nm", "-D", "--defined-only", m.LIBRARY_PATH], capture_output=True,
                          text=True, check=True).stdout
-    exported = set(re.findall(r"\bT (lb_[a-z_0-9]+)$", out, flags=re.M))
+    exported = set(re.findall(r"\bT (lb3?_[a-z_0-9]+)$", out, flags=re.M))
     missing = [n for n in declared_functions() if n not in exported]
     assert not missing, f"declared but not exported: {missing}"
-    from paper_2501_16000_amd import serve
-    assert sorted(m.EXPORTED + serve.EXPORTED) == declared_functions()
+    from paper_2501_16000_amd import oreg3, serve
+    assert sorted(m.EXPORTED + serve.EXPORTED + oreg3.EXPORTED) == declared_functions()
 
 
 def test_options_defaults_and_struct_layout():
@@ -128,3 +131,60 @@ def test_server_options_defaults_and_validation():
         assert serve.lb_server_create(ctypes.byref(o2), ctypes.byref(h)) == m.LB_EINVAL
     assert serve.lb_server_destroy(None) == m.LB_OK
     assert serve.lb_server_step(None, 1) == m.LB_EINVAL
+
+
+def test_lb3_options_defaults_and_struct_layout():
+    from paper_2501_16000_amd import oreg3
+    m = oreg()
+    o = oreg3.lb3_options()
+    oreg3.lb3_options_init(ctypes.byref(o))
+    assert (o.nx, o.ny, o.nz) == (0, 0, 0)
+    assert o.tau == 1.0 and abs(o.theta - 1 / 3) < 1e-16 and o.rho0 == 1.0
+    assert o.equilibrium == m.LB_EQ_GUIDED and o.storage == m.LB_F64
+    assert o.collision == m.LB_COLL_OREG and o.device == -1 and o.use_stream == 0
+    # 3 ints (+4 padding), 2 doubles, 3 enums (+4), double, pointer, 2 ints
+    assert ctypes.sizeof(oreg3.lb3_options) == 16 + 16 + 16 + 8 + 8 + 8
+
+
+INVALID3 = [
+    dict(nx=0), dict(ny=-2), dict(nz=0), dict(tau=0.5), dict(tau=math.nan), dict(theta=0.0),
+    dict(theta=1.0), dict(equilibrium=1, theta=0.4), dict(equilibrium=3), dict(storage=4),
+    dict(collision=2), dict(storage=1, rho0=0.0), dict(storage=3, rho0=math.nan),
+    dict(nx=64, ny=1 << 16, nz=1 << 16),
+]
+
+
+@pytest.mark.parametrize("bad", INVALID3)
+def test_lb3_create_rejects_invalid_options(bad):
+    from paper_2501_16000_amd import oreg3
+    m = oreg()
+    o = oreg3.lb3_options()
+    oreg3.lb3_options_init(ctypes.byref(o))
+    o.nx, o.ny, o.nz, o.tau = 8, 8, 8, 0.8
+    for k, v in bad.items():
+        setattr(o, k, v)
+    h = ctypes.c_void_p(123)
+    assert oreg3.lb3_create(ctypes.byref(o), ctypes.byref(h)) == m.LB_EINVAL
+    assert h.value is None
+    assert oreg3.lb3_last_error(None).decode()
+
+
+def test_lb3_null_arguments_and_no_device():
+    import torch
+    from paper_2501_16000_amd import oreg3
+    m = oreg()
+    assert oreg3.lb3_create(None, ctypes.byref(ctypes.c_void_p())) == m.LB_EINVAL
+    assert oreg3.lb3_step(None, 1) == m.LB_EINVAL
+    assert oreg3.lb3_init(None, None, None, None, None) == m.LB_EINVAL
+    assert oreg3.lb3_moments(None, None) == m.LB_EINVAL
+    assert oreg3.lb3_diagnostics(None, None) == m.LB_EINVAL
+    assert oreg3.lb3_sync(None) == m.LB_EINVAL
+    assert oreg3.lb3_destroy(None) == m.LB_OK
+    assert oreg3.lb3_time(None) == -1 and oreg3.lb3_device_bytes(None) == 0
+    if torch.cuda.device_count() == 0:
+        o = oreg3.lb3_options()
+        oreg3.lb3_options_init(ctypes.byref(o))
+        o.nx = o.ny = o.nz = 8
+        h = ctypes.c_void_p()
+        assert oreg3.lb3_create(ctypes.byref(o), ctypes.byref(h)) == m.LB_EDEVICE
+        assert h.value is None

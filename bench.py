@@ -14,6 +14,8 @@ Prints one JSON line (rank 0):
              stream), against 8 TB/s; traffic from rocprofv3 counters when
              profiles/ holds them for this kernel
   variants   the same workload with shifted FP32 / FP16 / BF16 storage
+  d3q27      the D3Q27 sweep on a 256^3 periodic box (shear wave normal to
+             (1, 1, 1)), every storage, against the HBM roofline
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the workload
 """
 from __future__ import annotations
@@ -33,6 +35,7 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector
 VALU_PEAK = 256 * 4 * 16 * 2.4e9  # lane-instructions/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 BYTES_PER_NODE = {"f64": 144, "f32s": 72, "f16s": 36, "bf16s": 36}
+STORAGE_BYTES = {"f64": 8, "f32s": 4, "f16s": 2, "bf16s": 2}
 # Time steps per fused launch (kernels.hip FusedLevels) and the algorithmic
 # flops of one guided-equilibrium OReg node update as implemented in
 # d2q9.hpp::collide (FMA = 2, the one division = 1): moments 22, equilibrium
@@ -60,6 +63,9 @@ def parse():
                    help="requests of the serving stream (0 skips the serving measurement)")
     p.add_argument("--serving-plain-sample", type=int, default=150,
                    help="requests of the stream also run one lattice per launch in FP64")
+    p.add_argument("--d3q27-n", type=int, default=256,
+                   help="side of the D3Q27 box timed per storage (0 skips it)")
+    p.add_argument("--d3q27-steps", type=int, default=100)
     p.add_argument("--pmc-workload", action="store_true",
                    help="only run a few sweeps per storage plus a 1 GiB device copy "
                         "(the workload profiled with rocprofv3 --pmc)")
@@ -91,7 +97,11 @@ def time_lattice(oreg, torch, n, tau, storage, steps, warmup, fields, fuse_steps
     return ms, diag
 
 
-def load_traffic(storage, n, nbytes_alg, fused=False):
+SOURCES_2D = ("kernels.hip", "d2q9.hpp")
+SOURCES_3D = ("kernels3.hip", "d3q27.hpp", "d2q9.hpp")
+
+
+def load_traffic(storage, n, nbytes_alg, fused=False, d3=False):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     covers this kernel build; else None."""
     try:
@@ -99,22 +109,72 @@ def load_traffic(storage, n, nbytes_alg, fused=False):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    entry = t.get("kernels", {}).get(("fused_" if fused else "") + storage)
-    if not entry or entry.get("n") != n or entry.get("kernel_source_sha") != kernel_source_sha():
+    key = ("d3q27_" if d3 else "") + ("fused_" if fused else "") + storage
+    entry = t.get("kernels", {}).get(key)
+    sha = kernel_source_sha(SOURCES_3D if d3 else SOURCES_2D)
+    if not entry or entry.get("n") != n or entry.get("kernel_source_sha") != sha:
         return None
     return entry.get("hbm_bytes_per_launch")
 
 
-def kernel_source_sha():
+def kernel_source_sha(files=SOURCES_2D):
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "d2q9.hpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2501_16000_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
+def time_box(oreg3, torch, n, tau, storage, steps, warmup, fields):
+    """Elapsed ms of `steps` D3Q27 sweeps (HIP events on the sweeps' stream)."""
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream), \
+            oreg3.Lattice3(n, n, n, tau, 1.0 / 3.0, storage=storage, stream=stream) as box:
+        box.init(*fields)
+        box.step(warmup)
+        torch.cuda.synchronize()
+        start = torch.cuda.Event(enable_timing=True)
+        end = torch.cuda.Event(enable_timing=True)
+        start.record(stream)
+        box.step(steps)
+        end.record(stream)
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end)
+        diag = box.diagnostics()
+    return ms, diag
+
+
+def d3q27_bench(torch, n, tau, steps):
+    """The D3Q27 sweep (one launch per step) on an n^3 box, every storage."""
+    from paper_2501_16000_amd import oreg3, workloads
+    fields = workloads.shear_wave3(n, 0.05)
+    out = {"workload": f"D3Q27 periodic {n}^3 OReg sweep, shear wave u0=0.05 normal to "
+                       f"(1,1,1), guided equilibrium, theta=1/3, tau={tau}, one box per launch",
+           "kernel": "sweep3_kernel<guided, OReg, storage>", "steps": steps}
+    for st in ("f64", "f32s", "f16s", "bf16s"):
+        ms, diag = time_box(oreg3, torch, n, tau, st, steps, 10, fields)
+        if diag[6] != 0:
+            raise RuntimeError(f"non-finite populations in the D3Q27 {st} run")
+        launch_s = ms / 1e3 / steps
+        alg = 2 * 27 * STORAGE_BYTES[st] * n ** 3
+        ach = alg / launch_s / 1e9
+        out[st] = {"value": round(n ** 3 / launch_s / 1e6, 1), "unit": "MLUPS",
+                   "ms_per_step": round(launch_s * 1e3, 5),
+                   "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                                "traffic": load_traffic(st, n, alg, d3=True),
+                                "algorithmic_bytes_per_launch": alg}}
+    return out
+
+
 COPY_BYTES = 1 << 30
+D3_PMC_N = 256
+
+
+def workloads_shear_wave3(n):
+    from paper_2501_16000_amd import workloads
+    return workloads.shear_wave3(n, 0.05)
 
 
 def pmc_workload(oreg, torch, n, tau, fields):
@@ -123,6 +183,10 @@ def pmc_workload(oreg, torch, n, tau, fields):
     for st in ("f64", "f32s", "bf16s"):
         time_lattice(oreg, torch, n, tau, st, 12, 0, fields)              # fused launches
         time_lattice(oreg, torch, n, tau, st, 5, 2, fields, fuse_steps=1)  # single steps
+    from paper_2501_16000_amd import oreg3
+    f3 = workloads_shear_wave3(D3_PMC_N)
+    for st in ("f64", "f32s", "bf16s"):
+        time_box(oreg3, torch, D3_PMC_N, tau, st, 5, 2, f3)
     src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
     src.fill_(1)
@@ -162,20 +226,24 @@ def summarize_pmc(fetch_csv, write_csv, n):
            "kernel_source_sha": kernel_source_sha(), "kernels": {}}
     sts = {"Storage<0>": "f64", "Storage<1>": "f32s", "Storage<2>": "f16s", "Storage<3>": "bf16s"}
     for k, v in fetch.items():
-        if "sweep_kernel" not in k or "batched" in k:
+        if "sweep" not in k or "batched" in k:
             continue
         st = next((name for tag, name in sts.items() if tag in k), None)
         if st is None or k not in write:
             continue
         fb = v * 1024.0 * f_scale
         wb = write[k] * 1024.0 * w_scale
-        key = ("fused_" if "fused_sweep_kernel" in k else "") + st
-        out["kernels"][key] = {"n": n, "kernel_source_sha": kernel_source_sha(),
+        d3 = "sweep3_kernel" in k
+        key = ("d3q27_" if d3 else "") + ("fused_" if "fused_sweep_kernel" in k else "") + st
+        side = D3_PMC_N if d3 else n
+        alg = (2 * 27 * STORAGE_BYTES[st] * side ** 3) if d3 else BYTES_PER_NODE[st] * n * n
+        out["kernels"][key] = {"n": side,
+                               "kernel_source_sha": kernel_source_sha(SOURCES_3D if d3 else SOURCES_2D),
                                "kernel": k.split("(")[0],
-                              "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
-                              "hbm_bytes_per_launch": fb + wb,
-                              "algorithmic_bytes_per_launch": BYTES_PER_NODE[st] * n * n,
-                              "fetch_kib_raw": v, "write_kib_raw": write[k]}
+                               "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                               "hbm_bytes_per_launch": fb + wb,
+                               "algorithmic_bytes_per_launch": alg,
+                               "fetch_kib_raw": v, "write_kib_raw": write[k]}
     with open(TRAFFIC_FILE, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps(out, indent=1))
@@ -370,6 +438,8 @@ def main():
         "single_step": single,
         "variants": variants,
     }
+    if args.d3q27_n > 0:
+        line["d3q27"] = d3q27_bench(torch, args.d3q27_n, tau, args.d3q27_steps)
     if args.serving_requests > 0:
         line["serving"] = serving_bench(oreg, args.serving_requests, args.serving_plain_sample)
     if not args.no_cpu_baseline:

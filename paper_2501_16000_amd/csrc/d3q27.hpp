@@ -152,7 +152,7 @@ __host__ __device__ __forceinline__ void collide(R (&f)[27], const Coeffs<R>& k)
   R drho, j[3], M[6];
   moments(f, drho, j, M);
   const R rho = SHIFTED ? k.rho0 + drho : drho;
-  const R inv = R(1) / rho;
+  const R inv = recip(rho);
   const R u[3] = {j[0] * inv, j[1] * inv, j[2] * inv};
   const R u2[3] = {u[0] * u[0], u[1] * u[1], u[2] * u[2]};
 

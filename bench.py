@@ -57,7 +57,7 @@ def parse():
                    help="other storages to time on the same workload ('' for none)")
     p.add_argument("--variant-steps", type=int, default=300)
     p.add_argument("--no-cpu-baseline", action="store_true")
-    p.add_argument("--cpu-steps", type=int, default=10,
+    p.add_argument("--cpu-steps", type=int, default=60,
                    help="oracle steps on the full lattice for the CPU baseline")
     p.add_argument("--serving-requests", type=int, default=2000,
                    help="requests of the serving stream (0 skips the serving measurement)")
@@ -410,12 +410,25 @@ def main():
                                   min(args.warmup, 20), fields)
         vsec = vms / 1e3
         v_ach = BYTES_PER_NODE[st] * cells / (vsec / args.variant_steps) / 1e9
-        variants[st] = {"value": round(cells * args.variant_steps / vsec / 1e6, 1),
-                        "unit": "MLUPS", "steps": args.variant_steps,
-                        "ms_per_step": round(vms / args.variant_steps, 5),
-                        "achieved_GBs": round(v_ach, 1),
-                        "frac": round(v_ach / HBM_PEAK_GBS, 4),
-                        "mass_drift_rel": float(abs(vdiag[0] - diag[0]) / diag[0])}
+        entry = {"value": round(cells * args.variant_steps / vsec / 1e6, 1),
+                 "unit": "MLUPS", "steps": args.variant_steps,
+                 "ms_per_step": round(vms / args.variant_steps, 5),
+                 "mass_drift_rel": float(abs(vdiag[0] - diag[0]) / diag[0])}
+        if FUSED_K[st] > 1:
+            # K steps per launch: bounded by VALU issue, not by HBM
+            tf = FLOPS_PER_UPDATE * cells * args.variant_steps / vsec / 1e12
+            entry["roofline"] = {"bound": "alu", "achieved": round(tf, 2),
+                                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": round(tf / FP32_PEAK_TFLOPS, 4),
+                                 "kernel": f"fused_sweep_kernel<K={FUSED_K[st]}, {st}>",
+                                 "hbm_algorithmic_GBs_per_launch": round(v_ach / FUSED_K[st], 1)}
+        else:
+            entry["roofline"] = {"bound": "hbm", "achieved": round(v_ach, 1),
+                                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                 "frac": round(v_ach / HBM_PEAK_GBS, 4),
+                                 "kernel": f"sweep_kernel<{st}>",
+                                 "traffic": load_traffic(st, n, BYTES_PER_NODE[st] * cells)}
+        variants[st] = entry
 
     line = {
         "metric": METRIC,

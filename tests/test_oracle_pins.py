@@ -190,6 +190,78 @@ def test_oreg_at_rest_is_projected_regularization():
         np.testing.assert_allclose(oracle.oreg_cell("poly2", 1 / 3, f), pr, atol=1e-17)
 
 
+@pytest.mark.parametrize("eq", ["guided", "poly2"])
+def test_worked_one_cell_collision(eq):
+    """The hand-worked collision of tests/golden/one_cell_oreg_rest.txt."""
+    rows = []
+    with open(os.path.join(GOLDEN, "one_cell_oreg_rest.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            i, fin, fpost = line.split()
+            rows.append((int(i), float(Fraction(fin)), float(Fraction(fpost))))
+    f = np.array([r[1] for r in rows])
+    expect = np.array([r[2] for r in rows])
+    np.testing.assert_allclose(oracle.collide_cell(eq, 0.8, 1 / 3, f), expect, rtol=2e-15, atol=0)
+
+
+def brute_force_step(f, tau, theta, eq):
+    """One time step written out with plain Python loops and no reuse: for
+    every node and every i the moments, the equilibrium of every k (Eq. (11)
+    as printed, or the Sec. III.D bracket), f^neq and S (Eq. (6), D = 2) are
+    recomputed; then Eq. (7) and the push to x + c_i."""
+    _, ny, nx = f.shape
+    c = [(0, 0), (1, 0), (0, 1), (-1, 0), (0, -1), (1, 1), (-1, 1), (-1, -1), (1, -1)]
+    out = np.zeros_like(f)
+
+    def feq(k, rho, u):
+        if eq == "poly2":
+            t0 = 1.0 / 3.0
+            W = 1.0
+            for a in range(2):
+                W *= (1 - t0) if c[k][a] == 0 else t0 / 2
+            cu = u[0] * c[k][0] + u[1] * c[k][1]
+            return rho * W * (1 + cu / t0 + cu * cu / (2 * t0 * t0) - (u[0] ** 2 + u[1] ** 2) / (2 * t0))
+        p = rho
+        for a in range(2):
+            ca = c[k][a]
+            p *= (1 - 2 * ca * ca) / 2 ** (ca * ca) * (ca * ca - 1 + ca * u[a] + u[a] ** 2 + theta)
+        return p
+
+    th = theta if eq == "guided" else 1.0 / 3.0
+    for y in range(ny):
+        for x in range(nx):
+            fl = [float(f[k, y, x]) for k in range(9)]
+            for i in range(9):
+                rho = sum(fl)
+                u = [sum(c[k][a] * fl[k] for k in range(9)) / rho for a in range(2)]
+                S = [[sum((c[k][a] * c[k][b] - (c[k][0] ** 2 + c[k][1] ** 2) / 2 * (a == b))
+                          * (fl[k] - feq(k, rho, u)) for k in range(9)) for b in range(2)]
+                     for a in range(2)]
+                C = [c[i][a] - u[a] for a in range(2)]
+                acc = sum((C[a] * C[b] - (C[0] ** 2 + C[1] ** 2) / 2 * (a == b)) * S[a][b]
+                          for a in range(2) for b in range(2))
+                fo = feq(i, rho, u) / (2 * rho * th * th) * acc
+                post = feq(i, rho, u) + (1 - 1 / tau) * fo
+                out[i, (y + c[i][1]) % ny, (x + c[i][0]) % nx] = post
+    return out
+
+
+@pytest.mark.parametrize("shape,eq,theta", [((8, 8), "guided", 1 / 3), ((5, 7), "guided", 0.4),
+                                            ((6, 1), "poly2", 1 / 3)])
+def test_brute_force_evaluator_agrees(shape, eq, theta):
+    """Cross-check of the oracle against an unhoisted pure-Python evaluation of
+    the same equations over 10 steps."""
+    ny, nx = shape
+    f0 = perturbed_state(eq, theta, ny, nx, 50, amp=1e-3)
+    tau = 0.7
+    ref = f0.copy()
+    for _ in range(10):
+        ref = brute_force_step(ref, tau, theta, eq)
+    got = oracle.run(f0, 10, tau, theta, eq)
+    np.testing.assert_allclose(got, ref, rtol=1e-14, atol=1e-16)
+
+
 def test_stress_inner_sum_is_trace_free():
     rng = np.random.default_rng(9)
     for _ in range(20):

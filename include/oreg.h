@@ -130,7 +130,10 @@ lb_status lb_init(lb_lattice* h, const double* rho, const double* ux, const doub
 
 /* lb_init from device arrays (e.g. torch tensors).  Enqueued on the
    lattice's stream; waits for it to validate the fields (LB_EINVAL as in
-   lb_init, in which case the state is left uninitialized). */
+   lb_init, in which case the state is left uninitialized).  The arrays must
+   be completely written when the lattice's stream reaches the init: work
+   that produces them on another stream is not waited for, so synchronize
+   that stream first (or create the lattice on it with use_stream). */
 lb_status lb_init_device(lb_lattice* h, const double* rho, const double* ux,
                          const double* uy);
 
@@ -144,7 +147,9 @@ lb_status lb_step(lb_lattice* h, int64_t n);
    Waits for the stream. */
 lb_status lb_moments(lb_lattice* h, double* out);
 
-/* Same into a device array out_dev[3][ny][nx]; enqueued, asynchronous. */
+/* Same into a device array out_dev[3][ny][nx]; enqueued, asynchronous: the
+   values are there once the lattice's stream has reached this point
+   (lb_sync, or an event on that stream). */
 lb_status lb_moments_device(lb_lattice* h, double* out_dev);
 
 /* Pre-collision populations f(x, t), unshifted, FP64: host double

@@ -76,7 +76,9 @@ lb_status lb3_init(lb3_lattice* h, const double* rho, const double* ux, const do
                    const double* uz);
 
 /* lb3_init from device arrays; waits for the lattice's stream to validate
-   them (LB_EINVAL leaves the lattice uninitialized). */
+   them (LB_EINVAL leaves the lattice uninitialized).  The arrays must be
+   completely written when the lattice's stream reaches the init: work on
+   other streams is not waited for (synchronize the producer first). */
 lb_status lb3_init_device(lb3_lattice* h, const double* rho, const double* ux,
                           const double* uy, const double* uz);
 

@@ -127,6 +127,14 @@ def _is_device_tensor(a) -> bool:
     return hasattr(a, "is_cuda") and a.is_cuda
 
 
+def _ready(tensors) -> None:
+    """Wait for torch's current stream on the tensors' device: the library
+    reads them on the lattice's own stream, which is not ordered after
+    torch's work."""
+    import torch
+    torch.cuda.current_stream(tensors[0].device).synchronize()
+
+
 def _device_ptr(t, shape) -> int:
     import torch
     if t.dtype != torch.float64 or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
@@ -209,6 +217,7 @@ class Lattice:
         shape = (self.ny, self.nx)
         if _is_device_tensor(rho):
             ptrs = [_device_ptr(a, shape) for a in (rho, ux, uy)]
+            _ready([rho, ux, uy])
             check(lb_init_device(self._h, *ptrs), self._h)
             return
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (rho, ux, uy)]
@@ -229,7 +238,9 @@ class Lattice:
         With ``out`` a float64 device tensor the gather is enqueued
         asynchronously into it; otherwise a numpy array is returned."""
         if out is not None and _is_device_tensor(out):
-            check(lb_moments_device(self._h, _device_ptr(out, (3, self.ny, self.nx))), self._h)
+            ptr = _device_ptr(out, (3, self.ny, self.nx))
+            _ready([out])
+            check(lb_moments_device(self._h, ptr), self._h)
             return out
         res = np.empty((3, self.ny, self.nx))
         check(lb_moments(self._h, _ptr(res)), self._h)

@@ -127,6 +127,7 @@ class Lattice3:
         """f(x, 0) = f^eq(rho, u): numpy arrays or float64 device tensors [nz, ny, nx]."""
         if oreg._is_device_tensor(rho):
             ptrs = [oreg._device_ptr(a, self.shape) for a in (rho, ux, uy, uz)]
+            oreg._ready([rho, ux, uy, uz])
             check(lb3_init_device(self._h, *ptrs), self._h)
             return
         arrs = [np.ascontiguousarray(a, dtype=np.float64) for a in (rho, ux, uy, uz)]
@@ -144,7 +145,9 @@ class Lattice3:
     def moments(self, out=None):
         """rho, ux, uy, uz of the pre-collision state, [4, nz, ny, nx]."""
         if out is not None and oreg._is_device_tensor(out):
-            check(lb3_moments_device(self._h, oreg._device_ptr(out, (4, *self.shape))), self._h)
+            ptr = oreg._device_ptr(out, (4, *self.shape))
+            oreg._ready([out])
+            check(lb3_moments_device(self._h, ptr), self._h)
             return out
         res = np.empty((4, *self.shape))
         check(lb3_moments(self._h, _ptr(res)), self._h)

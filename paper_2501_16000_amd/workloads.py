@@ -33,7 +33,8 @@ import numpy as np
 
 __all__ = [
     "shear_wave", "shear_wave_k2", "paper_shear_wave", "shocktube",
-    "shear_wave3", "shear_wave3_k2", "shear_wave3_projection",
+    "shear_wave3", "shear_wave3_k2", "shear_wave3_projection", "shear_wave_at",
+    "shear_wave3_at",
     "smooth_random_velocity", "noise", "ServingRequest", "serving_requests",
 ]
 
@@ -54,6 +55,23 @@ def shear_wave(n: int, u0: float, rho: float = 1.0, mode: int = 1):
     amp = u0 * np.sin(2.0 * np.pi * s)
     e_perp = np.array([-1.0, 2.0]) / math.sqrt(5.0)
     return (np.full((n, n), float(rho)), amp * e_perp[0], amp * e_perp[1])
+
+
+def shear_wave_at(x, y, n: int, u0: float, xp=np):
+    """Fields of ``shear_wave(n, u0)`` at nodes (x, y) (arrays of any shape);
+    ``xp`` is the array namespace (numpy, or torch for fields built on the
+    device).  Returns ``(rho, ux, uy)``."""
+    s = (2.0 * x + y) / n
+    amp = u0 * xp.sin(2.0 * math.pi * s)
+    rho = xp.ones_like(amp)
+    return rho, amp * (-1.0 / math.sqrt(5.0)), amp * (2.0 / math.sqrt(5.0))
+
+
+def shear_wave3_at(x, y, z, n: int, u0: float, xp=np):
+    """Fields of ``shear_wave3(n, u0)`` (cube) at nodes (x, y, z)."""
+    s = (x + y + z) / n
+    amp = u0 * xp.sin(2.0 * math.pi * s)
+    return xp.ones_like(amp), amp * _E3[0], amp * _E3[1], amp * 0.0
 
 
 def shear_wave_k2(n: int, mode: int = 1) -> float:

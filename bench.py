@@ -350,19 +350,37 @@ def serving_bench(oreg, count, plain_sample):
     }
 
 
-def cpu_baseline(n, tau, steps, fields):
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(n, tau, steps, fields, single_steps=2):
     import numpy as np
 
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1)
-    f = oracle.init("guided", 1.0 / 3.0, *fields)
+    f0 = oracle.init("guided", 1.0 / 3.0, *fields)
     t0 = time.perf_counter()
-    f = oracle.run(f, steps, tau, 1.0 / 3.0, "guided", nthreads=threads)
+    f = oracle.run(f0, steps, tau, 1.0 / 3.0, "guided", nthreads=threads)
     dt = time.perf_counter() - t0
+    assert np.isfinite(f[0, 0, 0])
+    t0 = time.perf_counter()
+    f = oracle.run(f0, single_steps, tau, 1.0 / 3.0, "guided", nthreads=1)
+    dt1 = time.perf_counter() - t0
     assert np.isfinite(f[0, 0, 0])
     return {"value": n * n * steps / dt / 1e6, "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"{n}x{n} rotated shear wave, FP64, guided, tau={tau}, {steps} steps "
-                      f"({dt:.1f} s, OpenMP over nodes)"}
+                      f"({dt:.1f} s, OpenMP over nodes, gcc -O2)",
+            "cpu_model": cpu_model(),
+            "single_thread": {"value": round(n * n * single_steps / dt1 / 1e6, 2), "unit": "MLUPS",
+                              "sample": f"{single_steps} steps of the same lattice ({dt1:.1f} s)"}}
 
 
 def main():
@@ -431,6 +449,15 @@ def main():
                            "device_copy_GBs": round(copy_gbs, 1),
                            "frac_of_device_copy": round(s_ach / copy_gbs, 4)}}
 
+    # the other relaxation times of the workload (same kernels, same work)
+    tau_sweep = {}
+    for t_other in (0.51, 1.0):
+        tms, tdiag = time_lattice(oreg, torch, n, t_other, args.storage, 300, 12, fields)
+        if tdiag[5] != 0:
+            raise RuntimeError(f"non-finite populations at tau={t_other}")
+        tau_sweep[str(t_other)] = {"value": round(cells * 300 / (tms / 1e3) / 1e6, 1),
+                                   "unit": "MLUPS", "steps": 300}
+
     variants = {}
     for st in [s for s in args.variants.split(",") if s and s != args.storage]:
         vms, vdiag = time_lattice(oreg, torch, n, tau, st, args.variant_steps,
@@ -476,6 +503,7 @@ def main():
                    "nx": n, "ny": n, "tau": tau, "storage": args.storage},
         "roofline": roofline,
         "single_step": single,
+        "tau_sweep": tau_sweep,
         "variants": variants,
     }
     if args.d3q27_n > 0:

@@ -206,9 +206,8 @@ const char* lb_last_error(const lb_lattice* h);
  * footprint is 2 * 9 * sizeof(storage) + 24 bytes per node) and returns
  * LB_EAGAIN otherwise, so the caller keeps the queue and retries as lattices
  * retire.  lb_server_step issues batched launches; one launch covers every
- * resident lattice and advances each by up to K time steps (K = 6 for LB_F64
- * and LB_F32S storage, 1 for the 16-bit formats; fewer in a lattice's last
- * launch), running the same per-node update as lb_step (Eqs. (6), (7) with the
+ * resident lattice and advances each by up to K = 6 time steps (fewer in a
+ * lattice's last launch), running the same per-node update as lb_step (Eqs. (6), (7) with the
  * server's equilibrium and storage and the request's tau).  Each lattice is
  * retired after its requested number of steps: its moments are gathered and
  * copied to pinned host memory asynchronously.  lb_server_poll reports finished results,

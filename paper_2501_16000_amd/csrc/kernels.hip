@@ -203,12 +203,11 @@ __global__ __launch_bounds__(SweepShape<ST>::BS) void sweep_kernel(
 // for bit.
 constexpr int kFusedRows = 64;  // output rows per wavefront
 
-// Fused levels per storage.  The 16-bit formats move 36 bytes per node update
-// and their single-step sweep is already faster than the fused one (which
-// spends VALU work on recomputed halos); they run one step per launch.
+// Fused levels per storage (every format fuses six steps; the specialisations
+// keep the choice per format explicit).
 template <int ST> struct FusedLevels { static constexpr int K = 6; };
-template <> struct FusedLevels<LB_F16S> { static constexpr int K = 1; };
-template <> struct FusedLevels<LB_BF16S> { static constexpr int K = 1; };
+template <> struct FusedLevels<LB_F16S> { static constexpr int K = 6; };
+template <> struct FusedLevels<LB_BF16S> { static constexpr int K = 6; };
 
 // lane l <- lane l - 1 (wave_shr:1) and lane l <- lane l + 1 (wave_shl:1).
 // Lanes without a source keep their own value; they are outside the valid

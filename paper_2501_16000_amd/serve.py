@@ -116,7 +116,7 @@ class Server:
 
     def step(self, n: int = 1) -> None:
         """Issue up to n batched launches (each advances every resident lattice
-        by up to 6 time steps for F64/F32S storage, 1 for 16-bit storage)."""
+        by up to 6 time steps)."""
         self._check(lb_server_step(self._h, int(n)))
 
     def poll(self):

@@ -315,7 +315,10 @@ FUSED_CASES = [
     (130, 3, "poly2", 1 / 3, 0.7, "bgk", "bounceback", "f64"),
     (513, 130, "guided", 1 / 3, 0.6, "oreg", "periodic", "f32s"),
     (200, 40, "poly2", 1 / 3, 0.7, "oreg", "periodic", "f16s"),
+    (1000, 130, "guided", 1 / 3, 0.6, "oreg", "periodic", "f16s"),
+    (301, 67, "guided", 0.4, 0.55, "bgk", "bounceback", "f16s"),
     (97, 33, "guided", 0.35, 0.8, "oreg", "bounceback", "bf16s"),
+    (640, 96, "poly2", 1 / 3, 0.9, "oreg", "periodic", "bf16s"),
 ]
 
 

@@ -145,30 +145,6 @@ def time_box(oreg3, torch, n, tau, storage, steps, warmup, fields):
     return ms, diag
 
 
-def copy_ceiling(torch, nbytes, reps=20):
-    """GB/s (read + write counted) of a plain device-to-device copy moving the
-    same bytes as one single-step sweep: the practical HBM ceiling."""
-    half = nbytes // 2
-    src = torch.empty(half, dtype=torch.uint8, device="cuda")
-    dst = torch.empty_like(src)
-    src.fill_(1)
-    stream = torch.cuda.Stream()
-    with torch.cuda.stream(stream):
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        start = torch.cuda.Event(enable_timing=True)
-        end = torch.cuda.Event(enable_timing=True)
-        start.record(stream)
-        for _ in range(reps):
-            dst.copy_(src)
-        end.record(stream)
-        torch.cuda.synchronize()
-    sec = start.elapsed_time(end) / 1e3 / reps
-    del src, dst
-    return 2 * half / sec / 1e9
-
-
 def d3q27_bench(torch, n, tau, steps):
     """The D3Q27 sweep (one launch per step) on an n^3 box, every storage."""
     from paper_2501_16000_amd import oreg3, workloads
@@ -204,12 +180,12 @@ def workloads_shear_wave3(n):
 def pmc_workload(oreg, torch, n, tau, fields):
     """A few sweeps per storage and one plain 1 GiB device-to-device copy, the
     calibration of the HBM counters."""
-    for st in ("f64", "f32s", "bf16s"):
+    for st in ("f64", "f32s", "f16s", "bf16s"):
         time_lattice(oreg, torch, n, tau, st, 12, 0, fields)              # fused launches
         time_lattice(oreg, torch, n, tau, st, 5, 2, fields, fuse_steps=1)  # single steps
     from paper_2501_16000_amd import oreg3
     f3 = workloads_shear_wave3(D3_PMC_N)
-    for st in ("f64", "f32s", "bf16s"):
+    for st in ("f64", "f32s", "f16s", "bf16s"):
         time_box(oreg3, torch, D3_PMC_N, tau, st, 5, 2, f3)
     src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
@@ -439,15 +415,12 @@ def main():
                           fuse_steps=1)
     s_launch = sms / 1e3 / min(args.steps, 300)
     s_ach = alg_bytes / s_launch / 1e9
-    copy_gbs = copy_ceiling(torch, alg_bytes)
     single = {"value": round(cells / s_launch / 1e6, 1), "unit": "MLUPS",
               "kernel": f"sweep_kernel<guided, OReg, periodic, {args.storage}>",
               "roofline": {"bound": "hbm", "achieved": round(s_ach, 1), "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": round(s_ach / HBM_PEAK_GBS, 4),
                            "traffic": load_traffic(args.storage, n, alg_bytes),
-                           "algorithmic_bytes_per_launch": alg_bytes,
-                           "device_copy_GBs": round(copy_gbs, 1),
-                           "frac_of_device_copy": round(s_ach / copy_gbs, 4)}}
+                           "algorithmic_bytes_per_launch": alg_bytes}}
 
     # the other relaxation times of the workload (same kernels, same work)
     tau_sweep = {}

@@ -194,3 +194,34 @@ def test_other_storages_equal_single_lattice_path(storage):
             L.init(*workloads.shear_wave(r.n, r.u0))
             L.step(r.steps)
             np.testing.assert_array_equal(got[r.rid], L.moments())
+
+
+@pytest.mark.parametrize("storage", ["f32s", "f64", "bf16s"])
+def test_degenerate_and_non_square_lattices(storage):
+    """Rows and columns of one node, odd and non-square sizes, in one mix:
+    each result equals lb_step on the same lattice bit for bit."""
+    oreg, serve = mods()
+    shapes = [(1, 7), (5, 1), (1, 1), (64, 3), (3, 64), (129, 65), (33, 200)]
+    rng = np.random.default_rng(17)
+    cases = []
+    for k, (nx, ny) in enumerate(shapes):
+        rho = 1.0 + 0.05 * rng.uniform(-1, 1, (ny, nx))
+        ux = 0.03 * rng.uniform(-1, 1, (ny, nx))
+        uy = 0.03 * rng.uniform(-1, 1, (ny, nx))
+        cases.append((k, rho, ux, uy, float(rng.uniform(0.55, 1.1)), int(rng.integers(1, 40))))
+    say(f"[serve] {storage}: degenerate and non-square lattices")
+    got = {}
+    with serve.Server(memory_budget=1 << 28, storage=storage) as srv:
+        for k, rho, ux, uy, tau, steps in cases:
+            assert srv.submit(k, rho, ux, uy, tau, steps)
+        while len(got) < len(cases):
+            srv.step(4)
+            srv.sync()
+            while (res := srv.poll()) is not None:
+                got[res.tag] = srv.fetch(res)
+    for k, rho, ux, uy, tau, steps in cases:
+        ny, nx = rho.shape
+        with oreg.Lattice(nx, ny, tau, storage=storage) as L:
+            L.init(rho, ux, uy)
+            L.step(steps)
+            np.testing.assert_array_equal(got[k], L.moments())

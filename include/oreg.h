@@ -292,7 +292,8 @@ lb_status lb_server_sync(lb_server* s);
 /* Free the server (waits for its work).  NULL-safe. */
 lb_status lb_server_destroy(lb_server* s);
 
-/* Message of the last failing call on s ("" if none). */
+/* Message of the last failing call on s ("" if none); for NULL, of the
+   calling thread's last failure that had no server handle (lb_server_create). */
 const char* lb_server_last_error(const lb_server* s);
 
 #ifdef __cplusplus

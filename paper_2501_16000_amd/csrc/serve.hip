@@ -147,6 +147,8 @@ struct lb_server {
 
 namespace {
 
+thread_local std::string t_server_err;  // last failure without a server handle
+
 lb_status fail(lb_server* s, lb_status st, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -154,6 +156,7 @@ lb_status fail(lb_server* s, lb_status st, const char* fmt, ...) {
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
   if (s) s->err = buf;
+  else t_server_err = buf;
   return st;
 }
 
@@ -350,19 +353,25 @@ lb_status lb_server_create(const lb_server_options* o, lb_server** out) {
   lo.rho0 = o->rho0;
   if (o->memory_budget <= 0 || o->pinned_bytes <= 0 || o->max_active < 1 ||
       o->max_active > 65536)
-    return LB_EINVAL;
-  if (o->equilibrium != LB_EQ_GUIDED && o->equilibrium != LB_EQ_POLY2) return LB_EINVAL;
-  if (o->storage < LB_F64 || o->storage > LB_BF16S) return LB_EINVAL;
-  if (!std::isfinite(o->theta)) return LB_EINVAL;
-  if (o->equilibrium == LB_EQ_GUIDED && !(o->theta > 0.0 && o->theta < 1.0)) return LB_EINVAL;
-  if (o->equilibrium == LB_EQ_POLY2 && std::fabs(o->theta - 1.0 / 3.0) > 1e-12) return LB_EINVAL;
-  if (o->storage != LB_F64 && (!std::isfinite(o->rho0) || !(o->rho0 > 0.0))) return LB_EINVAL;
+    return fail(nullptr, LB_EINVAL, "need memory_budget > 0, pinned_bytes > 0, 1 <= max_active <= 65536");
+  if (o->equilibrium != LB_EQ_GUIDED && o->equilibrium != LB_EQ_POLY2)
+    return fail(nullptr, LB_EINVAL, "unknown equilibrium %d", (int)o->equilibrium);
+  if (o->storage < LB_F64 || o->storage > LB_BF16S)
+    return fail(nullptr, LB_EINVAL, "unknown storage %d", (int)o->storage);
+  if (!std::isfinite(o->theta)) return fail(nullptr, LB_EINVAL, "theta must be finite");
+  if (o->equilibrium == LB_EQ_GUIDED && !(o->theta > 0.0 && o->theta < 1.0))
+    return fail(nullptr, LB_EINVAL, "guided equilibrium needs 0 < theta < 1 (got %g)", o->theta);
+  if (o->equilibrium == LB_EQ_POLY2 && std::fabs(o->theta - 1.0 / 3.0) > 1e-12)
+    return fail(nullptr, LB_EINVAL, "polynomial equilibrium needs theta = 1/3");
+  if (o->storage != LB_F64 && (!std::isfinite(o->rho0) || !(o->rho0 > 0.0)))
+    return fail(nullptr, LB_EINVAL, "rho0 must be finite and > 0 for shifted storage");
 
   int ndev = 0;
-  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return LB_EDEVICE;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1)
+    return fail(nullptr, LB_EDEVICE, "no HIP device available");
   int dev = o->device;
   if (dev < 0 && hipGetDevice(&dev) != hipSuccess) dev = 0;
-  if (dev >= ndev) return LB_EINVAL;
+  if (dev >= ndev) return fail(nullptr, LB_EINVAL, "device %d out of range (%d devices)", dev, ndev);
 
   lb_server* s = new (std::nothrow) lb_server;
   if (!s) return LB_ENOMEM;
@@ -463,8 +472,13 @@ lb_status lb_server_submit(lb_server* s, const lb_request* r) {
   std::memcpy(pin + cells, r->ux, (size_t)cells * sizeof(double));
   std::memcpy(pin + 2 * cells, r->uy, (size_t)cells * sizeof(double));
   const LatticeDesc d = describe(s, L);
+  // Error exits give back everything the request holds (after the streams
+  // have let go of the pinned upload block and the arena block).
   auto undo = [&](lb_status e) {
+    (void)hipStreamSynchronize(s->copy);
+    (void)hipStreamSynchronize(s->compute);
     s->arena.release(dev_off, dev_bytes);
+    s->pin_in_arena.release(in_off, in_bytes);
     free_lattice(L);
     return e;
   };
@@ -474,14 +488,14 @@ lb_status lb_server_submit(lb_server* s, const lb_request* r) {
       (e = hipEventRecord(L->upload_done, s->copy)) != hipSuccess ||
       (e = hipStreamWaitEvent(s->compute, L->upload_done, 0)) != hipSuccess)
     return undo(hfail(s, e, "upload event"));
-  L->upload_pending = true;
-  s->uploading.push_back(L);
   const Geometry g{L->nx, L->ny, cells};
   // The fields were validated above, so init_kernel's invalid-node counter
   // is never incremented and not read back.
   e = launch_init(s->opt.equilibrium, s->opt.storage, d.fields, d.fields + cells,
                   d.fields + 2 * cells, d.buf[0], g, d.coef, s->d_bad, s->compute);
-  if (e != hipSuccess) return hfail(s, e, "launch_init");
+  if (e != hipSuccess) return undo(hfail(s, e, "launch_init"));
+  L->upload_pending = true;
+  s->uploading.push_back(L);
   s->active.push_back(L);
   s->dirty = true;
   return LB_OK;
@@ -635,6 +649,8 @@ lb_status lb_server_destroy(lb_server* s) {
   return LB_OK;
 }
 
-const char* lb_server_last_error(const lb_server* s) { return s ? s->err.c_str() : ""; }
+const char* lb_server_last_error(const lb_server* s) {
+  return s ? s->err.c_str() : t_server_err.c_str();
+}
 
 }  // extern "C"

@@ -129,6 +129,7 @@ def test_server_options_defaults_and_validation():
         serve.lb_server_options_init(ctypes.byref(o2))
         setattr(o2, field, bad)
         assert serve.lb_server_create(ctypes.byref(o2), ctypes.byref(h)) == m.LB_EINVAL
+        assert serve.lb_server_last_error(None).decode()
     assert serve.lb_server_destroy(None) == m.LB_OK
     assert serve.lb_server_step(None, 1) == m.LB_EINVAL
 

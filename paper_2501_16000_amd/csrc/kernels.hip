@@ -810,9 +810,11 @@ bool fused_worthwhile(int st, int nx, int ny) {
                         ((ny + kFusedRows - 1) / kFusedRows);
   // A wavefront's row pipeline takes about 0.1 ms, so the fused sweep needs
   // enough wavefronts to fill the GPU before it beats the single-step sweep
-  // (measured crossovers on MI355X: about 900^2 nodes for F64, 1300^2 for
-  // F32S, where the single-step sweep runs from the 256 MB last-level cache).
-  const int64_t min_items = (st == LB_F64) ? 300 : 600;
+  // (measured crossovers on MI355X: about 1000^2 nodes for F64, 1400^2 for
+  // F32S and 2300^2 for F16S/BF16S, whose single-step sweep moves the fewest
+  // bytes; below them the single-step sweep runs from the 256 MB last-level
+  // cache).
+  const int64_t min_items = (st == LB_F64) ? 300 : (st == LB_F32S) ? 600 : 1600;
   return items >= min_items;
 }
 

@@ -60,19 +60,6 @@ __host__ __device__ __forceinline__ int wrap_sub(int v, int c, int n) {
 }
 
 // ---------------------------------------------------------------- sweep --
-// Nodes per lane: the 16-bit formats take two adjacent nodes per lane so that
-// every load and store is 4 bytes wide (a wavefront covers 128 nodes).
-template <int ST> struct Sweep3Shape { static constexpr int VX = 1; };
-template <> struct Sweep3Shape<LB_F16S> { static constexpr int VX = 2; };
-template <> struct Sweep3Shape<LB_BF16S> { static constexpr int VX = 2; };
-
-template <typename V, typename T>
-__device__ __forceinline__ V load_vec(const T* p) {  // any 2-byte alignment
-  V v;
-  __builtin_memcpy(&v, p, sizeof(V));
-  return v;
-}
-
 template <int EQ, int COLL, int ST>
 __global__ __launch_bounds__(kThreads) void sweep3_kernel(const typename Storage<ST>::T* __restrict__ src,
                                                           typename Storage<ST>::T* __restrict__ dst,
@@ -81,8 +68,6 @@ __global__ __launch_bounds__(kThreads) void sweep3_kernel(const typename Storage
   using S = Storage<ST>;
   using R = typename S::R;
   using T = typename S::T;
-  constexpr int VX = Sweep3Shape<ST>::VX;
-  typedef T Vec __attribute__((ext_vector_type(VX)));
   const unsigned int task =
       blockIdx.x * kWaves + (unsigned int)__builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   if (task >= tasks) return;
@@ -90,8 +75,11 @@ __global__ __launch_bounds__(kThreads) void sweep3_kernel(const typename Storage
   const unsigned int seg = task - row * nseg;
   const int y = (int)(row % (unsigned int)g.ny);
   const int z = (int)(row / (unsigned int)g.ny);
-  const int nx = g.nx;
-  const int x0 = (int)(seg * 64u * VX) + (int)(threadIdx.x & 63) * VX;  // first node of the lane
+  const int x = (int)(seg * 64u) + (int)(threadIdx.x & 63);
+  const bool active = x < g.nx;
+  const int xc = active ? x : g.nx - 1;  // lanes past the row end load a valid node
+  const int xm = xc == 0 ? g.nx - 1 : xc - 1;
+  const int xp = xc == g.nx - 1 ? 0 : xc + 1;
   const int64_t P = g.cells;
   // Start of the source row of g_i(x - c_i) for each (c_y, c_z).
   int64_t rows[3][3];
@@ -99,50 +87,18 @@ __global__ __launch_bounds__(kThreads) void sweep3_kernel(const typename Storage
   for (int b = 0; b < 3; ++b)
 #pragma unroll
     for (int a = 0; a < 3; ++a)
-      rows[a][b] = ((int64_t)wrap_sub(z, b - 1, g.nz) * g.ny + wrap_sub(y, a - 1, g.ny)) * nx;
-  R f[VX][27];
-  if (x0 >= 1 && x0 + VX < nx) {
-    // interior: one (possibly unaligned) load of VX nodes per population
-    unroll<0, 27>([&](auto I) {
-      constexpr int vx = d3::cx(I.value), vy = d3::cy(I.value), vz = d3::cz(I.value);
-      const Vec v = load_vec<Vec>(src + I.value * P + rows[vy + 1][vz + 1] + (x0 - vx));
-#pragma unroll
-      for (int q = 0; q < VX; ++q) f[q][I.value] = S::load(v[q]);
-    });
-  } else {
-    // x edges (periodic wrap) and lanes past the row end (they load a valid
-    // node and store nothing)
-#pragma unroll
-    for (int q = 0; q < VX; ++q) {
-      const int xc = x0 + q < nx ? x0 + q : nx - 1;
-      const int xm = xc == 0 ? nx - 1 : xc - 1;
-      const int xp = xc == nx - 1 ? 0 : xc + 1;
-      unroll<0, 27>([&](auto I) {
-        constexpr int vx = d3::cx(I.value), vy = d3::cy(I.value), vz = d3::cz(I.value);
-        const T* p = src + I.value * P + rows[vy + 1][vz + 1];
-        f[q][I.value] = S::load(p[vx == 0 ? xc : (vx > 0 ? xm : xp)]);
-      });
-    }
-  }
+      rows[a][b] = ((int64_t)wrap_sub(z, b - 1, g.nz) * g.ny + wrap_sub(y, a - 1, g.ny)) * g.nx;
+  R f[27];
+  unroll<0, 27>([&](auto I) {
+    constexpr int vx = d3::cx(I.value), vy = d3::cy(I.value), vz = d3::cz(I.value);
+    const T* p = src + I.value * P + rows[vy + 1][vz + 1];
+    f[I.value] = S::load(p[vx == 0 ? xc : (vx > 0 ? xm : xp)]);
+  });
   const Coeffs<R> k(c);
-#pragma unroll
-  for (int q = 0; q < VX; ++q) d3::collide<EQ, COLL, S::shifted>(f[q], k);
-  T* out = dst + rows[1][1];
-  const bool aligned = (VX == 1) || ((((rows[1][1] + x0) | P) & (VX - 1)) == 0);
-  if (x0 + VX <= nx && aligned) {
-    unroll<0, 27>([&](auto I) {
-      Vec v;
-#pragma unroll
-      for (int q = 0; q < VX; ++q) v[q] = S::store(f[q][I.value]);
-      __builtin_nontemporal_store(v, reinterpret_cast<Vec*>(out + I.value * P + x0));
-    });
-  } else {
-#pragma unroll
-    for (int q = 0; q < VX; ++q) {
-      if (x0 + q < nx) {
-        unroll<0, 27>([&](auto I) { out[I.value * P + x0 + q] = S::store(f[q][I.value]); });
-      }
-    }
+  d3::collide<EQ, COLL, S::shifted>(f, k);
+  if (active) {
+    T* q = dst + rows[1][1] + x;
+    unroll<0, 27>([&](auto I) { __builtin_nontemporal_store(S::store(f[I.value]), q + I.value * P); });
   }
 }
 
@@ -324,14 +280,17 @@ unsigned int blocks_for(int64_t n) { return (unsigned int)((n + kThreads - 1) / 
 }  // namespace
 
 // ------------------------------------------------------------ launchers --
+int64_t sweep3_tasks(const Geometry3& g) {
+  return (int64_t)((g.nx + 63) / 64) * g.ny * g.nz;
+}
+
 hipError_t launch_sweep3(int eq, int coll, int st, const void* src, void* dst, const Geometry3& g,
                          const Coef64& c, hipStream_t s) {
+  const unsigned int nseg = (unsigned int)((g.nx + 63) / 64);
+  const unsigned int tasks = (unsigned int)sweep3_tasks(g);
+  const unsigned int nblocks = (tasks + kWaves - 1) / kWaves;
   return with_storage(st, [&](auto ST) {
     using T = typename Storage<ST.value>::T;
-    constexpr int seg_nodes = 64 * Sweep3Shape<ST.value>::VX;
-    const unsigned int nseg = (unsigned int)((g.nx + seg_nodes - 1) / seg_nodes);
-    const unsigned int tasks = nseg * (unsigned int)g.ny * (unsigned int)g.nz;
-    const unsigned int nblocks = (tasks + kWaves - 1) / kWaves;
     return with_eq(eq, [&](auto EQ) {
       return with_coll(coll, [&](auto CO) {
         sweep3_kernel<EQ.value, CO.value, ST.value><<<nblocks, kThreads, 0, s>>>(

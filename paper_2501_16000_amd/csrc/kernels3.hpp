@@ -23,6 +23,9 @@ struct Geometry3 {
 // only on the box size).
 constexpr int kDiag3Blocks = 1024;
 
+// Wavefront tasks of one sweep: 64-node segments of every x-row.
+int64_t sweep3_tasks(const Geometry3& g);
+
 // One time step src -> dst.
 hipError_t launch_sweep3(int eq, int coll, int st, const void* src, void* dst, const Geometry3& g,
                          const Coef64& c, hipStream_t s);

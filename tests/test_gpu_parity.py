@@ -149,6 +149,34 @@ def test_parity_sampled_4096_fp64(tau):
     assert d[5] == 0
 
 
+@pytest.mark.parametrize("storage,bound", [("f32s", 3e-7), ("f16s", 5e-5), ("bf16s", 1.5e-3)])
+def test_sampled_4096_reduced_precision(storage, bound):
+    """The 4096^2 workload in shifted reduced-precision storage, in the launch
+    configuration the benchmark times (fused six-step launches): sampled
+    nodes after 100 steps against the FP64 oracle on their dependency
+    patches, within the storage's rounding."""
+    oreg = lib()
+    n, tau, theta, steps = 4096, 0.6, 1 / 3, 100
+    say(f"[parity] 4096^2 {storage} sampled nodes, {steps} steps")
+    rho, ux, uy = workloads.shear_wave(n, 0.05)
+    with oreg.Lattice(n, n, tau, theta, storage=storage) as L:
+        L.init(rho, ux, uy)
+        L.step(steps)
+        m = L.moments()
+    rng = np.random.default_rng(9)
+    samples = [(0, 0), (n - 1, n - 1), (51, 63), (52, 64), (2000, 4095)] + \
+        [tuple(rng.integers(0, n, 2)) for _ in range(3)]
+    fields = np.stack([rho, ux, uy])
+    worst = 0.0
+    for (x0, y0) in samples:
+        pf = patch(fields, x0, y0, steps)
+        fp = oracle.run(oracle.init("guided", theta, pf[0], pf[1], pf[2]), steps, tau, theta)
+        mp = oracle.moments(fp)[:, steps, steps]
+        worst = max(worst, float(np.max(np.abs(m[:, y0, x0] - mp))))
+    say(f"  max |moment difference| over {len(samples)} nodes: {worst:.3e}")
+    assert worst < bound
+
+
 def test_fixed_point_and_mass_at_full_size():
     oreg = lib()
     n = 4096

@@ -258,7 +258,8 @@ def serving_bench(oreg, count, plain_sample):
        moments in host memory) and aggregate MLUPS over the run;
     3. the plain path on the first requests of the same stream: one FP64
        lattice per request, lb_step over all its steps, one lattice at a time;
-       and the decay-rate error of the served (FP32S) results against it."""
+       and the decay-rate error of the served (FP32S) results against it;
+    4. the saturated stream on an FP64 server, and its decay-rate error."""
     import math
 
     import numpy as np
@@ -273,11 +274,17 @@ def serving_bench(oreg, count, plain_sample):
     stream = workloads.serving_requests(count=count, seed=16000, rate_hz=rate)
     with serve.Server(memory_budget=16 << 30, max_active=256, storage="f32s") as srv:
         rep = serve.run_stream(srv, stream, realtime=True, keep_results=False)
+    # the same saturated stream on an FP64 server (results equal lb_step bit
+    # for bit)
+    with serve.Server(memory_budget=64 << 30, max_active=256, storage="f64") as srv:
+        sat64 = serve.run_stream(srv, base, realtime=False)
     # plain one-lattice-per-launch FP64 path on a sample, and decay errors
     sample = base[:plain_sample]
-    served = {}
+    served, served64 = {}, {}
     with serve.Server(memory_budget=16 << 30, max_active=256, storage="f32s") as srv:
         served = serve.run_stream(srv, sample, realtime=False, keep_results=True).results
+    with serve.Server(memory_budget=64 << 30, max_active=256, storage="f64") as srv:
+        served64 = serve.run_stream(srv, sample, realtime=False, keep_results=True).results
     t0 = time.perf_counter()
     plain_lup, plain = 0, {}
     for r in sample:
@@ -287,7 +294,7 @@ def serving_bench(oreg, count, plain_sample):
             plain[r.rid] = lat.moments()
         plain_lup += r.n * r.n * r.steps
     plain_s = time.perf_counter() - t0
-    errs, errs_strong = [], []
+    errs, errs_strong, errs64 = [], [], []
     for r in sample:
         e_perp, phase = workloads.shear_wave_projection(r.n)
 
@@ -301,6 +308,7 @@ def serving_bench(oreg, count, plain_sample):
         if 0.05 <= ln_ref <= math.log(1e4):
             e = abs(math.log(a0 / amp(served[r.rid])) / ln_ref - 1)
             errs.append(e)
+            errs64.append(abs(math.log(a0 / amp(served64[r.rid])) / ln_ref - 1))
             if ln_ref <= math.log(1e2):
                 errs_strong.append(e)
     return {
@@ -323,6 +331,10 @@ def serving_bench(oreg, count, plain_sample):
             "p50": float(np.median(errs)) if errs else None,
             "max_where_aT_over_a0_ge_1e-2": float(max(errs_strong)) if errs_strong else None,
             "samples_aT_over_a0_ge_1e-2": len(errs_strong)},
+        "f64_server": {
+            "saturated_mlups": round(sat64.mlups, 1),
+            "decay_rate_error_max_same_window": float(max(errs64)) if errs64 else None,
+            "note": "FP64 storage, same stream and window; results equal lb_step bit for bit"},
     }
 
 

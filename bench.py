@@ -437,7 +437,7 @@ def main():
     # spread: five more timed runs of 300 steps each
     reps = []
     for _ in range(5):
-        rms, _ = time_lattice(oreg, torch, n, tau, args.storage, 300, 12, fields)
+        rms, _ = time_lattice(oreg, torch, n, tau, args.storage, 300, args.warmup, fields)
         reps.append(cells * 300 / (rms / 1e3) / 1e6)
     reps.sort()
     repeats = {"n": 5, "steps": 300, "median": round(reps[2], 1), "min": round(reps[0], 1),
@@ -446,7 +446,7 @@ def main():
     # the other relaxation times of the workload (same kernels, same work)
     tau_sweep = {}
     for t_other in (0.51, 1.0):
-        tms, tdiag = time_lattice(oreg, torch, n, t_other, args.storage, 300, 12, fields)
+        tms, tdiag = time_lattice(oreg, torch, n, t_other, args.storage, 300, args.warmup, fields)
         if tdiag[5] != 0:
             raise RuntimeError(f"non-finite populations at tau={t_other}")
         tau_sweep[str(t_other)] = {"value": round(cells * 300 / (tms / 1e3) / 1e6, 1),

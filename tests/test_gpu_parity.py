@@ -341,6 +341,8 @@ FUSED_CASES = [
     (800, 1, "guided", 0.4, 0.6, "oreg", "bounceback", "f64"),
     (53, 71, "guided", 1 / 3, 0.9, "bgk", "periodic", "f64"),
     (130, 3, "poly2", 1 / 3, 0.7, "bgk", "bounceback", "f64"),
+    (52, 128, "guided", 1 / 3, 0.75, "oreg", "periodic", "f64"),    # exactly one strip, two row blocks
+    (104, 65, "guided", 0.35, 0.6, "oreg", "bounceback", "f64"),   # two strips, one row past a block
     (513, 130, "guided", 1 / 3, 0.6, "oreg", "periodic", "f32s"),
     (200, 40, "poly2", 1 / 3, 0.7, "oreg", "periodic", "f16s"),
     (1000, 130, "guided", 1 / 3, 0.6, "oreg", "periodic", "f16s"),

@@ -189,3 +189,22 @@ def test_lb3_null_arguments_and_no_device():
         h = ctypes.c_void_p()
         assert oreg3.lb3_create(ctypes.byref(o), ctypes.byref(h)) == m.LB_EDEVICE
         assert h.value is None
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path):
+    """A copy of the package without liboreg.so cannot be imported: there is no
+    other implementation to fall back to."""
+    import shutil
+    import sys
+    pkg = os.path.join(ROOT, "paper_2501_16000_amd")
+    dst = tmp_path / "paper_2501_16000_amd"
+    shutil.copytree(pkg, dst, ignore=shutil.ignore_patterns("*.so", "__pycache__", "csrc"))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "try:\n"
+            "    from paper_2501_16000_amd import oreg\n"
+            "except ImportError as e:\n"
+            "    print('IMPORTERROR', e)\n"
+            "else:\n"
+            "    print('LOADED', oreg.LIBRARY_PATH)\n") % str(tmp_path)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert "IMPORTERROR" in r.stdout and "liboreg.so" in r.stdout, r.stdout + r.stderr

@@ -103,8 +103,8 @@ typedef struct lb_options {
                                  that to be faster (register-resident
                                  multi-step sweep; same result bit for bit);
                                  1: one sweep launch per time step;
-                                 2: fused launches whenever the storage has
-                                 them (F64, F32S), whatever the size           */
+                                 2: fused launches (six steps each, every
+                                 storage) whatever the size                    */
 } lb_options;
 
 /* Defaults: 0 x 0, tau 1, theta 1/3, guided, LB_F64, OReg, periodic, rho0 1,

@@ -179,9 +179,9 @@ def test_invalid_requests():
 
 @pytest.mark.parametrize("storage", ["f64", "f16s"])
 def test_other_storages_equal_single_lattice_path(storage):
-    """F64 serving uses fused launches, 16-bit storage single-step launches; both
-    equal lb_step on one lattice bit for bit, also when a lattice's steps are
-    not a multiple of the fused step count."""
+    """F64 and F16S serving (batched fused launches) equal lb_step on one
+    lattice bit for bit, also when a lattice's steps are not a multiple of the
+    fused step count."""
     oreg, serve = mods()
     reqs = [workloads.ServingRequest(0, 0.0, 40, 0.7, 0.03, 31),
             workloads.ServingRequest(1, 0.0, 70, 0.9, 0.02, 12),

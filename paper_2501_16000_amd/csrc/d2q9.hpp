@@ -112,10 +112,12 @@ struct Coef64 {
 template <typename R>
 struct Coeffs {
   R theta, a0, a1, kappa0, omega, rho0;
-  R r0a0, r0a1;  // rho0 a0, rho0 a1
+  R r0a0, r0a1;        // rho0 a0, rho0 a1
+  R kappa_h, kappa_2;  // kappa0 / 2 and 2 kappa0 (exact scalings of kappa0 in R)
   __host__ __device__ explicit Coeffs(const Coef64& c)
       : theta((R)c.theta), a0((R)c.a0), a1((R)c.a1), kappa0((R)c.kappa0),
-        omega((R)c.omega), rho0((R)c.rho0), r0a0((R)(c.rho0 * c.a0)), r0a1((R)(c.rho0 * c.a1)) {}
+        omega((R)c.omega), rho0((R)c.rho0), r0a0((R)(c.rho0 * c.a0)), r0a1((R)(c.rho0 * c.a1)),
+        kappa_h(R(0.5) * (R)c.kappa0), kappa_2(R(2) * (R)c.kappa0) {}
 };
 
 // Per-axis factor selected by the velocity component c (-1, 0, +1).
@@ -179,9 +181,22 @@ __host__ __device__ __forceinline__ void equilibrium(R drho, R rho, R ux, R uy, 
                                                      const Coeffs<R>& k, R (&feq)[9],
                                                      R (&deq)[9]) {
 #pragma clang fp contract(off)
-  if constexpr (EQ == LB_EQ_GUIDED) {
-    // Per-axis factors of Eq. (11) as rest value + small difference:
-    // Psi(-1) = a1 + (u^2 - u)/2, Psi(0) = a0 - u^2, Psi(+1) = a1 + (u^2 + u)/2.
+  if constexpr (EQ == LB_EQ_GUIDED && !SHIFTED) {
+    // Per-axis factors of Eq. (11): Psi(+-1) = (a1 + u^2/2) +- u/2,
+    // Psi(0) = a0 - u^2; f^eq_i = (rho X) Y.
+    const R bx = k.a1 + R(0.5) * uxx, by = k.a1 + R(0.5) * uyy;
+    const R Xm = fmadd(R(-0.5), ux, bx), X0 = k.a0 - uxx, Xp = fmadd(R(0.5), ux, bx);
+    const R Ym = fmadd(R(-0.5), uy, by), Y0 = k.a0 - uyy, Yp = fmadd(R(0.5), uy, by);
+    const R rXm = rho * Xm, rX0 = rho * X0, rXp = rho * Xp;
+    unroll<0, 9>([&](auto I) {
+      constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
+      feq[I.value] = pick<cx>(rXm, rX0, rXp) * pick<cy>(Ym, Y0, Yp);
+      deq[I.value] = feq[I.value];
+    });
+  } else if constexpr (EQ == LB_EQ_GUIDED) {
+    // Shifted storage: the per-axis factors as rest value + small difference,
+    // Psi(-1) = a1 + (u^2 - u)/2, Psi(0) = a0 - u^2, Psi(+1) = a1 + (u^2 + u)/2,
+    // so that f^eq_i - w_i rho0 is formed from the differences.
     const R hx = R(0.5) * uxx, hy = R(0.5) * uyy;
     const R dXm = fmadd(R(-0.5), ux, hx), dX0 = -uxx, dXp = fmadd(R(0.5), ux, hx);
     const R dYm = fmadd(R(-0.5), uy, hy), dY0 = -uyy, dYp = fmadd(R(0.5), uy, hy);
@@ -189,26 +204,19 @@ __host__ __device__ __forceinline__ void equilibrium(R drho, R rho, R ux, R uy, 
     const R Ym = k.a1 + dYm, Y0 = k.a0 + dY0, Yp = k.a1 + dYp;
     // feq_i = (rho X) Y
     const R rXm = rho * Xm, rX0 = rho * X0, rXp = rho * Xp;
-    if constexpr (SHIFTED) {
-      // deq_i = rho X Y - rho0 ax ay = drho X Y + (rho0 dX) Y + (rho0 ax) dY
-      const R r0dXm = k.rho0 * dXm, r0dX0 = k.rho0 * dX0, r0dXp = k.rho0 * dXp;
-      const R a0dYm = k.r0a0 * dYm, a0dY0 = k.r0a0 * dY0, a0dYp = k.r0a0 * dYp;
-      const R a1dYm = k.r0a1 * dYm, a1dY0 = k.r0a1 * dY0, a1dYp = k.r0a1 * dYp;
-      unroll<0, 9>([&](auto I) {
-        constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
-        const R X = pick<cx>(Xm, X0, Xp), Y = pick<cy>(Ym, Y0, Yp);
-        const R XY = X * Y;
-        feq[I.value] = pick<cx>(rXm, rX0, rXp) * Y;
-        const R adY = (cx == 0) ? pick<cy>(a0dYm, a0dY0, a0dYp) : pick<cy>(a1dYm, a1dY0, a1dYp);
-        deq[I.value] = fmadd(drho, XY, fmadd(pick<cx>(r0dXm, r0dX0, r0dXp), Y, adY));
-      });
-    } else {
-      unroll<0, 9>([&](auto I) {
-        constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
-        feq[I.value] = pick<cx>(rXm, rX0, rXp) * pick<cy>(Ym, Y0, Yp);
-        deq[I.value] = feq[I.value];
-      });
-    }
+    // deq_i = rho X Y - rho0 ax ay = (drho X + rho0 dX) Y + (rho0 ax) dY: every
+    // term is of the size of the deviation, so nothing cancels.
+    const R Exm = fmadd(drho, Xm, k.rho0 * dXm), Ex0 = fmadd(drho, X0, k.rho0 * dX0),
+            Exp = fmadd(drho, Xp, k.rho0 * dXp);
+    const R a0dYm = k.r0a0 * dYm, a0dY0 = k.r0a0 * dY0, a0dYp = k.r0a0 * dYp;
+    const R a1dYm = k.r0a1 * dYm, a1dY0 = k.r0a1 * dY0, a1dYp = k.r0a1 * dYp;
+    unroll<0, 9>([&](auto I) {
+      constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
+      const R Y = pick<cy>(Ym, Y0, Yp);
+      feq[I.value] = pick<cx>(rXm, rX0, rXp) * Y;
+      const R adY = (cx == 0) ? pick<cy>(a0dYm, a0dY0, a0dYp) : pick<cy>(a1dYm, a1dY0, a1dYp);
+      deq[I.value] = fmadd(pick<cx>(Exm, Ex0, Exp), Y, adY);
+    });
   } else {
     // Polynomial equilibrium at theta0 = 1/3: rho W_i (1 + P_i),
     // P_i = 3 c.u + 9/2 (c.u)^2 - 3/2 u^2.
@@ -240,9 +248,9 @@ __host__ __device__ __forceinline__ void collide(R (&f)[9], const Coeffs<R>& k) 
   // Eq. (2a).  Sum w_i = 1 and sum w_i c_i = 0, so the shift only enters rho.
   const R s13 = f[1] + f[3], s24 = f[2] + f[4], s57 = f[5] + f[7], s68 = f[6] + f[8];
   const R drho = f[0] + (s13 + s24) + (s57 + s68);
-  const R d57 = f[5] - f[7];
-  const R jx = (f[1] - f[3]) + d57 + (f[8] - f[6]);
-  const R jy = (f[2] - f[4]) + d57 + (f[6] - f[8]);
+  const R d57 = f[5] - f[7], d86 = f[8] - f[6];
+  const R jx = (f[1] - f[3]) + (d57 + d86);
+  const R jy = (f[2] - f[4]) + (d57 - d86);
   const R rho = SHIFTED ? k.rho0 + drho : drho;
   const R inv = recip(rho);
   const R ux = jx * inv, uy = jy * inv;
@@ -258,18 +266,19 @@ __host__ __device__ __forceinline__ void collide(R (&f)[9], const Coeffs<R>& k) 
   } else {
     // Trace-free non-equilibrium stress of Eq. (6) from second moments:
     // S_xx = -S_yy = s, S_xy.
-    const R s = R(0.5) * fmadd(-rho, uxx - uyy, s13 - s24);
+    // 2 s = (Pi_xx - Pi_yy) of f^neq and S_xy.
+    const R s2 = fmadd(-rho, uxx - uyy, s13 - s24);
     const R sxy = fmadd(-rho, ux * uy, s57 - s68);
     // Eqs. (6), (7): f^post_i = f^eq_i + kappa f^eq_i [s (Cx^2 - Cy^2) + 2 S_xy Cx Cy],
     // kappa = (1 - 1/tau)/(2 rho theta^2), C = c_i - u.  With ks = kappa s and
     // kt = 2 kappa S_xy the bracket splits into per-axis factors:
-    // kappa [..] = ks Cx^2 - ks Cy^2 + (kt Cx) Cy.
-    const R kappa = k.kappa0 * inv;
-    const R ks = kappa * s, kt = kappa * (sxy + sxy);
+    // kappa [..] = ks Cx^2 - ks Cy^2 + (kt Cx) Cy.  (kappa0/2) and (2 kappa0)
+    // are exact rescalings, so ks and kt round as kappa (s2/2) and kappa (2 S_xy).
+    const R ks = (k.kappa_h * inv) * s2, kt = (k.kappa_2 * inv) * sxy;
     const R Cxm = R(-1) - ux, Cx0 = -ux, Cxp = R(1) - ux;
     const R Cym = R(-1) - uy, Cy0 = -uy, Cyp = R(1) - uy;
-    const R axm = (ks * Cxm) * Cxm, ax0 = (ks * Cx0) * Cx0, axp = (ks * Cxp) * Cxp;
-    const R bym = (ks * Cym) * Cym, by0 = (ks * Cy0) * Cy0, byp = (ks * Cyp) * Cyp;
+    const R axm = (ks * Cxm) * Cxm, ax0 = ks * uxx, axp = (ks * Cxp) * Cxp;
+    const R bym = (ks * Cym) * Cym, by0 = ks * uyy, byp = (ks * Cyp) * Cyp;
     const R txm = kt * Cxm, tx0 = kt * Cx0, txp = kt * Cxp;
     unroll<0, 9>([&](auto I) {
       constexpr int cx = cx_of(I.value), cy = cy_of(I.value);

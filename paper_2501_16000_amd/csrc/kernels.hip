@@ -200,8 +200,12 @@ __global__ __launch_bounds__(SweepShape<ST>::BS) void sweep_kernel(
 // needed above and below the strip's H rows (K on each side) are recomputed
 // by the neighbouring strips.  Between levels the populations are rounded
 // through the storage format, so the result equals K single-step sweeps bit
-// for bit.
-constexpr int kFusedRows = 64;  // output rows per wavefront
+// for bit.  The 2K pipeline-fill rows are unrolled, so that which levels
+// produce is known at compile time, and the steady-state loop (three rows
+// per trip) has no branches apart from the store predicate.  H is a runtime
+// multiple of 3 chosen per lattice (fused_rows).
+constexpr int kFusedRows = 64;         // output rows per work item of the batched server sweep
+constexpr int kFusedRowsDefault = 66;  // output rows per wavefront of fused_sweep_kernel
 
 // Fused levels per storage (every format fuses six steps; the specialisations
 // keep the choice per format explicit).
@@ -234,14 +238,12 @@ __device__ __forceinline__ double from_right(double v) {
 template <int K, int EQ, int COLL, int BC, int ST>
 __global__ __launch_bounds__(256) void fused_sweep_kernel(
     const typename Storage<ST>::T* __restrict__ src, typename Storage<ST>::T* __restrict__ dst,
-    Geometry g, Coef64 c, int strips, int items) {
+    Geometry g, Coef64 c, int strips, int items, int H) {
   using S = Storage<ST>;
   using R = typename S::R;
   using Tt = typename S::T;
   constexpr int W = 64 - 2 * K;
-  constexpr int H = kFusedRows;
-  constexpr int J = H + 2 * K;  // rows of level 0 read per wavefront
-  static_assert(J % 2 == 0, "the row loop runs in pairs");
+  const int J = H + 2 * K;  // rows of level 0 read per wavefront (a multiple of 3)
   const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (wave >= items) return;  // whole wavefronts leave together
@@ -254,58 +256,66 @@ __global__ __launch_bounds__(256) void fused_sweep_kernel(
   const bool store_lane = lane >= K && lane < 64 - K && X0 - K + lane < nx;
   const bool wall = BC == LB_BC_BOUNCEBACK && (col == 0 || col == nx - 1);
   const Coeffs<R> k(c);
-  // Window of level lv: two row slots holding pops 0, 1, 2, 3, 5, 6 (pops 4,
-  // 7, 8 of a row are used as soon as it arrives).  Row j of a level lives in
-  // slot j % 2; with the row loop taken in pairs the slot roles are fixed at
-  // compile time and the window slides without register moves.
-  R Sl[K][2][6];
+  // Window of level lv: row j of the level lives in slot j % 3 and holds
+  // pops 0, 1, 2, 3, 5, 6 (pops 4, 7, 8 of a row are used as soon as it
+  // arrives).  With three slots and the row loop unrolled by three, a new row
+  // always goes to the slot of a row that is no longer read, so the slot
+  // roles are compile-time constants and the window slides without register
+  // moves.
+  R Sl[K][3][6];
   int row = (Y0 - K) % ny;
   if (row < 0) row += ny;
-  Tt nb[2][9];  // level-0 rows: the one in use and the one in flight
+  Tt nb[3][9];  // level-0 rows: row j is loaded into nb[j % 3] one row ahead
 #pragma unroll
   for (int i = 0; i < 9; ++i) nb[0][i] = src[i * P + (int64_t)row * nx + col];
 
-  auto one_row = [&](int j, auto PAR) {
-    constexpr int p = decltype(PAR)::value;  // j % 2
+  // One row step: row j of level 0 arrives and the first NP levels (those
+  // whose three source rows are complete, NP = min(K, j / 2)) produce a row
+  // of the next level.  NP is a compile-time constant: the fill steps are
+  // unrolled and the steady steps have NP = K.
+  auto one_row = [&](int j, auto SLOT, auto NPROD) {
+    constexpr int q = decltype(SLOT)::value;  // j % 3
+    constexpr int qa = (q + 1) % 3;           // slot of row j - 2
+    constexpr int qb = (q + 2) % 3;           // slot of row j - 1
+    constexpr int NP = decltype(NPROD)::value;
     R C[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) C[i] = S::load(nb[p][i]);
-    if (j + 1 < J) {  // prefetch the next row of level 0
-      row = wrap_inc(row, ny);
+    for (int i = 0; i < 9; ++i) C[i] = S::load(nb[q][i]);
+    // Prefetch the next row of level 0.  The last step reloads its own row
+    // (a cache hit) instead of skipping the load: an unconditional load
+    // leaves nothing of the old buffer alive.
+    if (j + 1 < J) row = wrap_inc(row, ny);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) nb[1 - p][i] = src[i * P + (int64_t)row * nx + col];
-    }
+    for (int i = 0; i < 9; ++i) nb[qa][i] = src[i * P + (int64_t)row * nx + col];
 #pragma unroll
     for (int lv = 0; lv < K; ++lv) {
-      const bool produce = j >= 2 * (lv + 1);  // level lv + 1 has its three source rows
+      // Slot q held row j - 3 of the level, which is no longer read.
+      Sl[lv][q][0] = C[0];
+      Sl[lv][q][1] = C[1];
+      Sl[lv][q][2] = C[2];
+      Sl[lv][q][3] = C[3];
+      Sl[lv][q][4] = C[5];
+      Sl[lv][q][5] = C[6];
+      if (lv >= NP) break;  // no rows of level lv + 1 yet
       R N[9];
-      if (produce) {
-        const R(&A)[6] = Sl[lv][p];      // row j - 2 (pops 2, 5, 6 used)
-        const R(&B)[6] = Sl[lv][1 - p];  // row j - 1 (pops 0, 1, 3 used)
-        N[0] = B[0];
-        N[1] = from_left(B[1]);
-        N[3] = from_right(B[3]);
-        N[2] = A[2];
-        N[5] = from_left(A[4]);
-        N[6] = from_right(A[5]);
-        N[4] = C[4];
-        N[7] = from_right(C[7]);
-        N[8] = from_left(C[8]);
-        if (wall) {
-          R r[9];
-          unroll<0, 9>([&](auto I) { r[I.value] = N[opp_of(I.value)]; });
-          unroll<0, 9>([&](auto I) { N[I.value] = r[I.value]; });
-        } else {
-          collide<EQ, COLL, S::shifted>(N, k);
-        }
+      const R(&A)[6] = Sl[lv][qa];  // row j - 2 (pops 2, 5, 6 used)
+      const R(&B)[6] = Sl[lv][qb];  // row j - 1 (pops 0, 1, 3 used)
+      N[0] = B[0];
+      N[1] = from_left(B[1]);
+      N[3] = from_right(B[3]);
+      N[2] = A[2];
+      N[5] = from_left(A[4]);
+      N[6] = from_right(A[5]);
+      N[4] = C[4];
+      N[7] = from_right(C[7]);
+      N[8] = from_left(C[8]);
+      if (wall) {
+        R r[9];
+        unroll<0, 9>([&](auto I) { r[I.value] = N[opp_of(I.value)]; });
+        unroll<0, 9>([&](auto I) { N[I.value] = r[I.value]; });
+      } else {
+        collide<EQ, COLL, S::shifted>(N, k);
       }
-      Sl[lv][p][0] = C[0];
-      Sl[lv][p][1] = C[1];
-      Sl[lv][p][2] = C[2];
-      Sl[lv][p][3] = C[3];
-      Sl[lv][p][4] = C[5];
-      Sl[lv][p][5] = C[6];
-      if (!produce) break;  // deeper levels have no rows yet
       if (lv + 1 == K) {
         const int y = Y0 + j - 2 * K;
         if (store_lane && y < ny) {
@@ -316,12 +326,22 @@ __global__ __launch_bounds__(256) void fused_sweep_kernel(
       } else {
 #pragma unroll
         for (int i = 0; i < 9; ++i) C[i] = S::load(S::store(N[i]));
+        // Materialise the level's row here: without this ordering point the
+        // compiler interleaves the collisions of the straight-line steady
+        // loop and runs out of registers.
+        __asm__ volatile("" : "+v"(C[0]), "+v"(C[1]), "+v"(C[2]), "+v"(C[3]), "+v"(C[4]),
+                         "+v"(C[5]), "+v"(C[6]), "+v"(C[7]), "+v"(C[8]));
       }
     }
   };
-  for (int j = 0; j < J; j += 2) {
-    one_row(j, IC<0>{});
-    one_row(j + 1, IC<1>{});
+  static_assert((2 * K) % 3 == 0, "the steady loop starts on slot 0");
+  // Pipeline fill: rows 0 .. 2K - 1, level lv + 1 starting at row 2 (lv + 1).
+  unroll<0, 2 * K>([&](auto JJ) { one_row(JJ.value, IC<JJ.value % 3>{}, IC<JJ.value / 2>{}); });
+  // Steady state: every level produces a row per step.
+  for (int j = 2 * K; j < J; j += 3) {
+    one_row(j, IC<0>{}, IC<K>{});
+    one_row(j + 1, IC<1>{}, IC<K>{});
+    one_row(j + 2, IC<2>{}, IC<K>{});
   }
 }
 
@@ -701,7 +721,8 @@ int fused_levels(int st) {
 }
 
 hipError_t launch_fused_sweep(int eq, int coll, int bc, int st, const void* src, void* dst,
-                              const Geometry& g, const Coef64& c, hipStream_t s) {
+                              const Geometry& g, const Coef64& c, int rows, hipStream_t s) {
+  if (rows < 3 || rows % 3 != 0) return hipErrorInvalidValue;
   return with_storage(st, [&](auto ST) -> hipError_t {
     using T = typename Storage<ST.value>::T;
     constexpr int K = FusedLevels<ST.value>::K;
@@ -710,20 +731,65 @@ hipError_t launch_fused_sweep(int eq, int coll, int bc, int st, const void* src,
     } else {
     constexpr int W = 64 - 2 * K;
     const int strips = (g.nx + W - 1) / W;
-    const int segs = (g.ny + kFusedRows - 1) / kFusedRows;
+    const int segs = (g.ny + rows - 1) / rows;
     const int items = strips * segs;
     const unsigned int nblocks = (unsigned int)((items + 3) / 4);
     return with_eq(eq, [&](auto EQ) {
       return with_coll(coll, [&](auto CO) {
         return with_bc(bc, [&](auto BC) {
           fused_sweep_kernel<K, EQ.value, CO.value, BC.value, ST.value><<<nblocks, 256, 0, s>>>(
-              static_cast<const T*>(src), static_cast<T*>(dst), g, c, strips, items);
+              static_cast<const T*>(src), static_cast<T*>(dst), g, c, strips, items, rows);
           return hipGetLastError();
         });
       });
     });
     }
   });
+}
+
+int fused_wave_slots(int st) {
+  int dev = 0, cus = 0, blocks = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const hipError_t e = with_storage(st, [&](auto ST) -> hipError_t {
+    constexpr int K = FusedLevels<ST.value>::K;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &blocks,
+        reinterpret_cast<const void*>(
+            &fused_sweep_kernel<K, LB_EQ_GUIDED, LB_COLL_OREG, LB_BC_PERIODIC, ST.value>),
+        256, 0);
+  });
+  if (e != hipSuccess) return 0;
+  return cus * blocks * 4;
+}
+
+int fused_rows(int st, int nx, int ny, int slots) {
+  const int K = fused_levels(st);
+  const int64_t strips = (nx + (64 - 2 * K) - 1) / (64 - 2 * K);
+  if (slots <= 0) return kFusedRowsDefault;
+  // Wavefronts of a launch occupy the chip's wave slots in rounds, and every
+  // wavefront repeats 2K rows of level 0 for its halo and fills its pipeline
+  // over K(K + 1) row collisions.  Choose the row count (a multiple of 3)
+  // that minimises rounds x (collisions per wavefront), counting a partial
+  // round as a full one.
+  int best = kFusedRowsDefault;
+  double best_cost = 0;
+  for (int rounds = 1; rounds <= 64; ++rounds) {
+    const int64_t segs = rounds * (int64_t)slots / strips;
+    if (segs < 1) continue;
+    int H = (int)((ny + segs - 1) / segs);
+    H = (H + 2) / 3 * 3;
+    if (H < 18) break;
+    const int64_t items = strips * ((ny + H - 1) / H);
+    const int64_t r = (items + slots - 1) / slots;
+    const double cost = (double)r * (K * (double)(H + 2 * K) - K * (K + 1));
+    if (best_cost == 0 || cost < best_cost) {
+      best_cost = cost;
+      best = H;
+    }
+  }
+  return best;
 }
 
 hipError_t launch_init(int eq, int st, const double* rho, const double* ux, const double* uy,

@@ -33,9 +33,18 @@ int fused_levels(int st);
 // Whether fused launches beat single-step launches for this lattice size.
 bool fused_worthwhile(int st, int nx, int ny);
 
-// fused_levels(st) time steps in one launch: src -> dst.
+// fused_levels(st) time steps in one launch: src -> dst; each wavefront
+// produces `rows` (a multiple of 3) output rows of a column strip.
 hipError_t launch_fused_sweep(int eq, int coll, int bc, int st, const void* src, void* dst,
-                              const Geometry& g, const Coef64& c, hipStream_t s);
+                              const Geometry& g, const Coef64& c, int rows, hipStream_t s);
+
+// Wavefronts of the fused sweep for storage st that the current device runs
+// at once (0 if the query fails).
+int fused_wave_slots(int st);
+
+// Output rows per wavefront of a fused launch on an nx x ny lattice, given
+// the device's wave slots.
+int fused_rows(int st, int nx, int ny, int slots);
 
 // g from fields (device FP64 [ny][nx] each); counts invalid input nodes
 // (non-finite value or rho <= 0) into *bad.

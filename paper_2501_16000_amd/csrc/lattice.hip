@@ -23,6 +23,7 @@ struct lb_lattice {
   int cur = 0;                        // buffer holding the current state
   size_t elem = 8;                    // bytes per stored population
   Geometry geo{};
+  int fused_rows = 66;                // output rows per wavefront of fused launches
   Coef64 coef{};
   double theta_energy = 0.0;          // theta of p = rho theta in the energy sum
   bool initialized = false;
@@ -240,6 +241,9 @@ lb_status lb_create_ex(const lb_options* opt, lb_lattice** out) {
   if (e != hipSuccess) return cleanup(hip_fail(nullptr, e, "hipMalloc(aux)"));
   e = hipMalloc((void**)&h->counter, sizeof(unsigned int));
   if (e != hipSuccess) return cleanup(hip_fail(nullptr, e, "hipMalloc(counter)"));
+  if (fused_levels(h->opt.storage) > 1)
+    h->fused_rows = fused_rows(h->opt.storage, h->geo.nx, h->geo.ny,
+                               fused_wave_slots(h->opt.storage));
   *out = h;
   return LB_OK;
 }
@@ -293,7 +297,7 @@ lb_status lb_step(lb_lattice* h, int64_t n) {
   while (K > 1 && left >= K) {
     HIP_TRY(h, launch_fused_sweep(h->opt.equilibrium, h->opt.collision, h->opt.boundary_x,
                                   h->opt.storage, h->buf[h->cur], h->buf[1 - h->cur], h->geo,
-                                  h->coef, h->stream));
+                                  h->coef, h->fused_rows, h->stream));
     h->cur = 1 - h->cur;
     h->t += K;
     left -= K;

@@ -204,7 +204,6 @@ __global__ __launch_bounds__(SweepShape<ST>::BS) void sweep_kernel(
 // produce is known at compile time, and the steady-state loop (three rows
 // per trip) has no branches apart from the store predicate.  H is a runtime
 // multiple of 3 chosen per lattice (fused_rows).
-constexpr int kFusedRows = 64;         // output rows per work item of the batched server sweep
 constexpr int kFusedRowsDefault = 66;  // output rows per wavefront of fused_sweep_kernel
 
 // Fused levels per storage (every format fuses six steps; the specialisations
@@ -214,15 +213,15 @@ template <> struct FusedLevels<LB_F16S> { static constexpr int K = 6; };
 template <> struct FusedLevels<LB_BF16S> { static constexpr int K = 6; };
 
 // lane l <- lane l - 1 (wave_shr:1) and lane l <- lane l + 1 (wave_shl:1).
-// Lanes without a source keep their own value; they are outside the valid
-// region of the next level anyway.
+// Lanes without a source are outside the valid region of the next level: in
+// FP32 they read zero (bound_ctrl), which lets the compiler fold the shift
+// into the arithmetic instruction that consumes it; in FP64 (two 32-bit
+// moves, no folding) they keep their own value.
 __device__ __forceinline__ float from_left(float v) {
-  const int b = __float_as_int(v);
-  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x138, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float from_right(float v) {
-  const int b = __float_as_int(v);
-  return __int_as_float(__builtin_amdgcn_update_dpp(b, b, 0x130, 0xF, 0xF, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xF, 0xF, true));
 }
 __device__ __forceinline__ double from_left(double v) {
   const int lo = __double2loint(v), hi = __double2hiint(v);
@@ -235,27 +234,22 @@ __device__ __forceinline__ double from_right(double v) {
                           __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xF, 0xF, false));
 }
 
-template <int K, int EQ, int COLL, int BC, int ST>
-__global__ __launch_bounds__(256) void fused_sweep_kernel(
-    const typename Storage<ST>::T* __restrict__ src, typename Storage<ST>::T* __restrict__ dst,
-    Geometry g, Coef64 c, int strips, int items, int H) {
+// One wavefront's strip: K time steps over the rows Y0 .. Y0 + H - 1 of the
+// columns X0 .. X0 + 63 - 2 KS (lane l holds column X0 - KS + l; KS >= K is
+// the strip's halo width, so lanes KS .. 63 - KS are stored).
+template <int K, int KS, int EQ, int COLL, int BC, int ST>
+__device__ __forceinline__ void fused_strip(const typename Storage<ST>::T* __restrict__ src,
+                                            typename Storage<ST>::T* __restrict__ dst, int nx,
+                                            int ny, int64_t P, int X0, int Y0, int H,
+                                            const Coeffs<typename Storage<ST>::R>& k, int lane) {
   using S = Storage<ST>;
   using R = typename S::R;
   using Tt = typename S::T;
-  constexpr int W = 64 - 2 * K;
-  const int J = H + 2 * K;  // rows of level 0 read per wavefront (a multiple of 3)
-  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int lane = threadIdx.x & 63;
-  if (wave >= items) return;  // whole wavefronts leave together
-  const int strip = wave % strips, seg = wave / strips;
-  const int X0 = strip * W, Y0 = seg * H;
-  const int nx = g.nx, ny = g.ny;
-  const int64_t P = g.plane;
-  int col = (X0 - K + lane) % nx;
+  const int J = H + 2 * K;  // rows of level 0 read (H is a multiple of 3)
+  int col = (X0 - KS + lane) % nx;
   if (col < 0) col += nx;
-  const bool store_lane = lane >= K && lane < 64 - K && X0 - K + lane < nx;
+  const bool store_lane = lane >= KS && lane < 64 - KS && X0 - KS + lane < nx;
   const bool wall = BC == LB_BC_BOUNCEBACK && (col == 0 || col == nx - 1);
-  const Coeffs<R> k(c);
   // Window of level lv: row j of the level lives in slot j % 3 and holds
   // pops 0, 1, 2, 3, 5, 6 (pops 4, 7, 8 of a row are used as soon as it
   // arrives).  With three slots and the row loop unrolled by three, a new row
@@ -268,6 +262,17 @@ __global__ __launch_bounds__(256) void fused_sweep_kernel(
   Tt nb[3][9];  // level-0 rows: row j is loaded into nb[j % 3] one row ahead
 #pragma unroll
   for (int i = 0; i < 9; ++i) nb[0][i] = src[i * P + (int64_t)row * nx + col];
+  // Output row y is stored one step after it is computed, before that step's
+  // prefetch: the wait for the prefetched row then covers only stores issued
+  // a whole step earlier, never the ones just issued.
+  Tt pend[9];
+  auto store_row = [&](int y) {
+    if (store_lane && y >= Y0 && y < ny) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+        __builtin_nontemporal_store(pend[i], dst + i * P + (int64_t)y * nx + col);
+    }
+  };
 
   // One row step: row j of level 0 arrives and the first NP levels (those
   // whose three source rows are complete, NP = min(K, j / 2)) produce a row
@@ -281,6 +286,12 @@ __global__ __launch_bounds__(256) void fused_sweep_kernel(
     R C[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) C[i] = S::load(nb[q][i]);
+    // Keep the first use of the row that arrives here at this step: without
+    // the ordering point the compiler hoists it into the previous step, right
+    // behind the load, and the wavefront waits for memory.
+    __asm__ volatile("" : "+v"(C[0]), "+v"(C[1]), "+v"(C[2]), "+v"(C[3]), "+v"(C[4]), "+v"(C[5]),
+                     "+v"(C[6]), "+v"(C[7]), "+v"(C[8]));
+    if constexpr (NP == K) store_row(Y0 + j - 1 - 2 * K);  // the previous step's output row
     // Prefetch the next row of level 0.  The last step reloads its own row
     // (a cache hit) instead of skipping the load: an unconditional load
     // leaves nothing of the old buffer alive.
@@ -317,12 +328,8 @@ __global__ __launch_bounds__(256) void fused_sweep_kernel(
         collide<EQ, COLL, S::shifted>(N, k);
       }
       if (lv + 1 == K) {
-        const int y = Y0 + j - 2 * K;
-        if (store_lane && y < ny) {
 #pragma unroll
-          for (int i = 0; i < 9; ++i)
-            __builtin_nontemporal_store(S::store(N[i]), dst + i * P + (int64_t)y * nx + col);
-        }
+        for (int i = 0; i < 9; ++i) pend[i] = S::store(N[i]);  // output row Y0 + j - 2K
       } else {
 #pragma unroll
         for (int i = 0; i < 9; ++i) C[i] = S::load(S::store(N[i]));
@@ -334,15 +341,29 @@ __global__ __launch_bounds__(256) void fused_sweep_kernel(
       }
     }
   };
-  static_assert((2 * K) % 3 == 0, "the steady loop starts on slot 0");
   // Pipeline fill: rows 0 .. 2K - 1, level lv + 1 starting at row 2 (lv + 1).
   unroll<0, 2 * K>([&](auto JJ) { one_row(JJ.value, IC<JJ.value % 3>{}, IC<JJ.value / 2>{}); });
   // Steady state: every level produces a row per step.
   for (int j = 2 * K; j < J; j += 3) {
-    one_row(j, IC<0>{}, IC<K>{});
-    one_row(j + 1, IC<1>{}, IC<K>{});
-    one_row(j + 2, IC<2>{}, IC<K>{});
+    one_row(j, IC<(2 * K) % 3>{}, IC<K>{});
+    one_row(j + 1, IC<(2 * K + 1) % 3>{}, IC<K>{});
+    one_row(j + 2, IC<(2 * K + 2) % 3>{}, IC<K>{});
   }
+  store_row(Y0 + J - 1 - 2 * K);
+}
+
+template <int K, int EQ, int COLL, int BC, int ST>
+__global__ __launch_bounds__(256) void fused_sweep_kernel(
+    const typename Storage<ST>::T* __restrict__ src, typename Storage<ST>::T* __restrict__ dst,
+    Geometry g, Coef64 c, int strips, int items, int H) {
+  constexpr int W = 64 - 2 * K;
+  const int wave = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (wave >= items) return;  // whole wavefronts leave together
+  const int strip = wave % strips, seg = wave / strips;
+  const Coeffs<typename Storage<ST>::R> k(c);
+  fused_strip<K, K, EQ, COLL, BC, ST>(src, dst, g.nx, g.ny, g.plane, strip * W, seg * H, H, k,
+                                      lane);
 }
 
 // Batched form of fused_sweep_kernel for the server: each wavefront takes one
@@ -355,7 +376,6 @@ __global__ __launch_bounds__(256) void batched_fused_kernel(const LatticeDesc* _
                                                             const int* __restrict__ map,
                                                             int64_t items, int64_t T) {
   using S = Storage<ST>;
-  using R = typename S::R;
   using Tt = typename S::T;
   constexpr int W = 64 - 2 * KMAX;
   const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -364,77 +384,18 @@ __global__ __launch_bounds__(256) void batched_fused_kernel(const LatticeDesc* _
   const LatticeDesc& L = d[map[item]];
   const int local = (int)(item - L.tile_begin);
   const int strip = local % L.strips, seg = local / L.strips;
-  const int kl = L.kl, H = L.rows;
-  const int X0 = strip * W, Y0 = seg * H;
-  const int nx = L.nx, ny = L.ny;
-  const int64_t P = L.plane;
+  const int H = L.rows;
   const int64_t t = T - L.admit_T;
   const Tt* __restrict__ src = static_cast<const Tt*>(L.buf[t & 1]);
   Tt* __restrict__ dst = static_cast<Tt*>(L.buf[(t + 1) & 1]);
-  int col = (X0 - KMAX + lane) % nx;
-  if (col < 0) col += nx;
-  const bool store_lane = lane >= KMAX && lane < 64 - KMAX && X0 - KMAX + lane < nx;
-  const Coeffs<R> k(L.coef);
-  R Sl[KMAX][2][6];
-  int row = (Y0 - kl) % ny;
-  if (row < 0) row += ny;
-  const int J = H + 2 * kl;  // even: H is even
-  Tt nb[2][9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) nb[0][i] = src[i * P + (int64_t)row * nx + col];
-
-  auto one_row = [&](int j, auto PAR) {
-    constexpr int p = decltype(PAR)::value;
-    R C[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) C[i] = S::load(nb[p][i]);
-    if (j + 1 < J) {
-      row = wrap_inc(row, ny);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) nb[1 - p][i] = src[i * P + (int64_t)row * nx + col];
-    }
-#pragma unroll
-    for (int lv = 0; lv < KMAX; ++lv) {
-      const bool produce = j >= 2 * (lv + 1);
-      R N[9];
-      if (produce) {
-        const R(&A)[6] = Sl[lv][p];
-        const R(&B)[6] = Sl[lv][1 - p];
-        N[0] = B[0];
-        N[1] = from_left(B[1]);
-        N[3] = from_right(B[3]);
-        N[2] = A[2];
-        N[5] = from_left(A[4]);
-        N[6] = from_right(A[5]);
-        N[4] = C[4];
-        N[7] = from_right(C[7]);
-        N[8] = from_left(C[8]);
-        collide<EQ, LB_COLL_OREG, S::shifted>(N, k);
-      }
-      Sl[lv][p][0] = C[0];
-      Sl[lv][p][1] = C[1];
-      Sl[lv][p][2] = C[2];
-      Sl[lv][p][3] = C[3];
-      Sl[lv][p][4] = C[5];
-      Sl[lv][p][5] = C[6];
-      if (!produce) break;
-      if (lv + 1 == kl) {
-        const int y = Y0 + j - 2 * kl;
-        if (store_lane && y < ny && y < Y0 + H) {
-#pragma unroll
-          for (int i = 0; i < 9; ++i)
-            __builtin_nontemporal_store(S::store(N[i]), dst + i * P + (int64_t)y * nx + col);
-        }
-        break;
-      }
-#pragma unroll
-      for (int i = 0; i < 9; ++i) C[i] = S::load(S::store(N[i]));
-    }
-  };
-  for (int j = 0; j < J; j += 2) {
-    one_row(j, IC<0>{});
-    one_row(j + 1, IC<1>{});
-  }
+  const Coeffs<typename S::R> k(L.coef);
+  // The step count is uniform over the wavefront: branch to the pipeline
+  // compiled for it.
+  unroll<1, KMAX + 1>([&](auto KL) {
+    if (L.kl == KL.value)
+      fused_strip<KL.value, KMAX, EQ, LB_COLL_OREG, LB_BC_PERIODIC, ST>(
+          src, dst, L.nx, L.ny, L.plane, strip * W, seg * H, H, k, lane);
+  });
 }
 
 // ----------------------------------------------------------------- init --
@@ -871,9 +832,9 @@ int fused_strip_width(int st) { return 64 - 2 * fused_levels(st); }
 
 bool fused_worthwhile(int st, int nx, int ny) {
   const int K = fused_levels(st);
-  if (K < 2 || ny < kFusedRows) return false;
+  if (K < 2 || ny < kFusedRowsDefault) return false;
   const int64_t items = (int64_t)((nx + (64 - 2 * K) - 1) / (64 - 2 * K)) *
-                        ((ny + kFusedRows - 1) / kFusedRows);
+                        ((ny + kFusedRowsDefault - 1) / kFusedRowsDefault);
   // A wavefront's row pipeline takes about 0.1 ms, so the fused sweep needs
   // enough wavefronts to fill the GPU before it beats the single-step sweep
   // (measured crossovers on MI355X: about 1000^2 nodes for F64, 1400^2 for

@@ -202,7 +202,7 @@ LatticeDesc describe(const lb_server* s, const ServedLattice* L) {
   d.admit_T = L->admit_T;
   const int W = fused_strip_width(s->opt.storage);
   d.kl = L->kl;
-  d.rows = L->ny < 64 ? L->ny + (L->ny & 1) : 64;  // even, so rows + 2 kl is even
+  d.rows = L->ny < 66 ? (L->ny + 2) / 3 * 3 : 66;  // a multiple of 3 (the strip loop's unroll)
   d.strips = (L->nx + W - 1) / W;
   d.coef = s->base;
   d.coef.kappa0 = (1.0 - 1.0 / L->tau) / (2.0 * s->base.theta * s->base.theta);

@@ -240,6 +240,77 @@ __host__ __device__ __forceinline__ void equilibrium(R drho, R rho, R ux, R uy, 
   }
 }
 
+// OReg update with the guided equilibrium, written on the per-axis factors:
+// f^eq_i = (rho X) Y with X = Psi(c_ix, u_x), Y = Psi(c_iy, u_y), and
+// f^post_i = f^eq_i (1 + ax - by + tx Cy) (Eqs. 6, 7; the bracket terms are
+// defined in collide below), evaluated as
+//   rho X (Y (1 - by) + Y ax + (Y Cy) tx)                  (unshifted), or
+//   deq_i + rho X (Y ax - Y by + (Y Cy) tx)                 (shifted),
+// with the per-y products formed once: three operations per population.
+// d13 = f1 + f3 - f2 - f4 and d57 = f5 + f7 - f6 - f8 (second moments).
+template <bool SHIFTED, typename R>
+__host__ __device__ __forceinline__ void collide_guided_oreg(R (&f)[9], const Coeffs<R>& k, R drho,
+                                                             R rho, R inv, R ux, R uy, R uxx,
+                                                             R uyy, R d13, R d57) {
+#pragma clang fp contract(off)
+  R Xm, X0, Xp, Ym, Y0, Yp;
+  R deq[9];
+  if constexpr (!SHIFTED) {
+    // Psi(+-1) = (a1 + u^2/2) +- u/2, Psi(0) = a0 - u^2.
+    const R gx = fmadd(R(0.5), uxx, k.a1), gy = fmadd(R(0.5), uyy, k.a1);
+    Xm = fmadd(R(-0.5), ux, gx), X0 = k.a0 - uxx, Xp = fmadd(R(0.5), ux, gx);
+    Ym = fmadd(R(-0.5), uy, gy), Y0 = k.a0 - uyy, Yp = fmadd(R(0.5), uy, gy);
+  } else {
+    // Rest value + small difference, so that deq_i = f^eq_i - w_i rho0 is
+    // formed from the differences: deq_i = (drho X + rho0 dX) Y + (rho0 ax) dY.
+    const R hx = R(0.5) * uxx, hy = R(0.5) * uyy;
+    const R dXm = fmadd(R(-0.5), ux, hx), dX0 = -uxx, dXp = fmadd(R(0.5), ux, hx);
+    const R dYm = fmadd(R(-0.5), uy, hy), dY0 = -uyy, dYp = fmadd(R(0.5), uy, hy);
+    Xm = k.a1 + dXm, X0 = k.a0 + dX0, Xp = k.a1 + dXp;
+    Ym = k.a1 + dYm, Y0 = k.a0 + dY0, Yp = k.a1 + dYp;
+    const R Exm = fmadd(drho, Xm, k.rho0 * dXm), Ex0 = fmadd(drho, X0, k.rho0 * dX0),
+            Exp = fmadd(drho, Xp, k.rho0 * dXp);
+    const R a0dYm = k.r0a0 * dYm, a0dY0 = k.r0a0 * dY0, a0dYp = k.r0a0 * dYp;
+    const R a1dYm = k.r0a1 * dYm, a1dY0 = k.r0a1 * dY0, a1dYp = k.r0a1 * dYp;
+    unroll<0, 9>([&](auto I) {
+      constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
+      const R adY = (cx == 0) ? pick<cy>(a0dYm, a0dY0, a0dYp) : pick<cy>(a1dYm, a1dY0, a1dYp);
+      deq[I.value] = fmadd(pick<cx>(Exm, Ex0, Exp), pick<cy>(Ym, Y0, Yp), adY);
+    });
+  }
+  const R rXm = rho * Xm, rX0 = rho * X0, rXp = rho * Xp;
+  // Non-equilibrium stress (2 s = Pi_xx - Pi_yy, S_xy) and the bracket of
+  // Eq. (6): kappa [..] = ks Cx^2 - ks Cy^2 + (kt Cx) Cy, C = c_i - u.
+  const R s2 = fmadd(-rho, uxx - uyy, d13);
+  const R sxy = fmadd(-rho, ux * uy, d57);
+  const R ks = (k.kappa_h * inv) * s2, kt = (k.kappa_2 * inv) * sxy;
+  const R Cxm = R(-1) - ux, Cx0 = -ux, Cxp = R(1) - ux;
+  const R Cym = R(-1) - uy, Cy0 = -uy, Cyp = R(1) - uy;
+  const R axm = (ks * Cxm) * Cxm, ax0 = ks * uxx, axp = (ks * Cxp) * Cxp;
+  const R bym = (ks * Cym) * Cym, by0 = ks * uyy, byp = (ks * Cyp) * Cyp;
+  const R txm = kt * Cxm, tx0 = kt * Cx0, txp = kt * Cxp;
+  const R Qm = Ym * Cym, Q0 = Y0 * Cy0, Qp = Yp * Cyp;  // Y Cy
+  if constexpr (!SHIFTED) {
+    const R Pm = fmadd(-Ym, bym, Ym), P0 = fmadd(-Y0, by0, Y0), Pp = fmadd(-Yp, byp, Yp);
+    unroll<0, 9>([&](auto I) {
+      constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
+      const R Y = pick<cy>(Ym, Y0, Yp);
+      const R v = fmadd(pick<cy>(Qm, Q0, Qp), pick<cx>(txm, tx0, txp),
+                        fmadd(Y, pick<cx>(axm, ax0, axp), pick<cy>(Pm, P0, Pp)));
+      f[I.value] = pick<cx>(rXm, rX0, rXp) * v;
+    });
+  } else {
+    const R Bm = Ym * bym, B0 = Y0 * by0, Bp = Yp * byp;
+    unroll<0, 9>([&](auto I) {
+      constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
+      const R Y = pick<cy>(Ym, Y0, Yp);
+      const R v = fmadd(pick<cy>(Qm, Q0, Qp), pick<cx>(txm, tx0, txp),
+                        fmadd(Y, pick<cx>(axm, ax0, axp), -pick<cy>(Bm, B0, Bp)));
+      f[I.value] = fmadd(pick<cx>(rXm, rX0, rXp), v, deq[I.value]);
+    });
+  }
+}
+
 // Collide one node in place.  f holds the pre-collision populations (shifted
 // by w_i rho0 when SHIFTED) and receives the post-collision ones (same shift).
 template <int EQ, int COLL, bool SHIFTED, typename R>
@@ -255,6 +326,11 @@ __host__ __device__ __forceinline__ void collide(R (&f)[9], const Coeffs<R>& k) 
   const R inv = recip(rho);
   const R ux = jx * inv, uy = jy * inv;
   const R uxx = ux * ux, uyy = uy * uy;
+
+  if constexpr (EQ == LB_EQ_GUIDED && COLL == LB_COLL_OREG) {
+    collide_guided_oreg<SHIFTED>(f, k, drho, rho, inv, ux, uy, uxx, uyy, s13 - s24, s57 - s68);
+    return;
+  }
 
   R feq[9], deq[9];
   equilibrium<EQ, SHIFTED>(drho, rho, ux, uy, uxx, uyy, k, feq, deq);

@@ -349,6 +349,10 @@ FUSED_CASES = [
     (301, 67, "guided", 0.4, 0.55, "bgk", "bounceback", "f16s"),
     (97, 33, "guided", 0.35, 0.8, "oreg", "bounceback", "bf16s"),
     (640, 96, "poly2", 1 / 3, 0.9, "oreg", "periodic", "bf16s"),
+    # several 66-row blocks per strip: ragged last block, exact multiple
+    (52, 300, "guided", 1 / 3, 0.7, "oreg", "periodic", "f64"),
+    (52, 198, "guided", 0.35, 0.6, "oreg", "periodic", "f32s"),
+    (60, 500, "guided", 1 / 3, 0.55, "oreg", "periodic", "bf16s"),
 ]
 
 

@@ -708,11 +708,12 @@ hipError_t launch_fused_sweep(int eq, int coll, int bc, int st, const void* src,
   });
 }
 
-int fused_wave_slots(int st) {
+FusedShape fused_shape(int st) {
+  FusedShape sh{0, 0};
   int dev = 0, cus = 0, blocks = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipGetDevice(&dev) != hipSuccess) return sh;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-    return 0;
+    return sh;
   const hipError_t e = with_storage(st, [&](auto ST) -> hipError_t {
     constexpr int K = FusedLevels<ST.value>::K;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(
@@ -721,32 +722,36 @@ int fused_wave_slots(int st) {
             &fused_sweep_kernel<K, LB_EQ_GUIDED, LB_COLL_OREG, LB_BC_PERIODIC, ST.value>),
         256, 0);
   });
-  if (e != hipSuccess) return 0;
-  return cus * blocks * 4;
+  if (e != hipSuccess) return sh;
+  sh.simds = cus * 4;
+  sh.waves_per_simd = blocks;  // 256-thread workgroups: one wavefront per SIMD each
+  return sh;
 }
 
-int fused_rows(int st, int nx, int ny, int slots) {
+double fused_cost(int st, int nx, int ny, int H, const FusedShape& sh) {
   const int K = fused_levels(st);
   const int64_t strips = (nx + (64 - 2 * K) - 1) / (64 - 2 * K);
-  if (slots <= 0) return kFusedRowsDefault;
-  // Wavefronts of a launch occupy the chip's wave slots in rounds, and every
-  // wavefront repeats 2K rows of level 0 for its halo and fills its pipeline
-  // over K(K + 1) row collisions.  Choose the row count (a multiple of 3)
-  // that minimises rounds x (collisions per wavefront), counting a partial
-  // round as a full one.
-  int best = kFusedRowsDefault;
-  double best_cost = 0;
-  for (int rounds = 1; rounds <= 64; ++rounds) {
-    const int64_t segs = rounds * (int64_t)slots / strips;
-    if (segs < 1) continue;
-    int H = (int)((ny + segs - 1) / segs);
-    H = (H + 2) / 3 * 3;
-    if (H < 18) break;
-    const int64_t items = strips * ((ny + H - 1) / H);
-    const int64_t r = (items + slots - 1) / slots;
-    const double cost = (double)r * (K * (double)(H + 2 * K) - K * (K + 1));
-    if (best_cost == 0 || cost < best_cost) {
-      best_cost = cost;
+  const int64_t items = strips * ((ny + H - 1) / H);
+  const int64_t w = (items + sh.simds - 1) / sh.simds;
+  const int64_t resident = w < sh.waves_per_simd ? w : sh.waves_per_simd;
+  const double work = K * (double)(H + 2 * K) - K * (K + 1) + 2 * K;
+  return (double)w / (1.0 + 0.08 * (double)(resident - 1)) * work;
+}
+
+int fused_rows(int st, int nx, int ny, const FusedShape& sh) {
+  if (sh.simds <= 0 || sh.waves_per_simd <= 0) return kFusedRowsDefault;
+  // One wavefront per SIMD already runs the pipeline near the SIMD's issue
+  // limit (measured: a second one adds 6-11 %), so a launch takes about w
+  // wavefront-times, w = ceil(work items / SIMDs), and one wavefront's time
+  // follows its row collisions, K (H + 2K) - K (K + 1), plus a start-up of
+  // about 2K.  H (a multiple of 3) minimises the modelled launch time.
+  const int hmax = ny < 3 * 1024 ? (ny + 2) / 3 * 3 : 3 * 1024;
+  int best = 3;
+  double best_cost = -1;
+  for (int H = 3; H <= hmax; H += 3) {
+    const double c = fused_cost(st, nx, ny, H, sh);
+    if (best_cost < 0 || c < best_cost) {
+      best_cost = c;
       best = H;
     }
   }
@@ -831,18 +836,11 @@ hipError_t launch_batched_sweep(int eq, int st, const LatticeDesc* d, const int*
 int fused_strip_width(int st) { return 64 - 2 * fused_levels(st); }
 
 bool fused_worthwhile(int st, int nx, int ny) {
-  const int K = fused_levels(st);
-  if (K < 2 || ny < kFusedRowsDefault) return false;
-  const int64_t items = (int64_t)((nx + (64 - 2 * K) - 1) / (64 - 2 * K)) *
-                        ((ny + kFusedRowsDefault - 1) / kFusedRowsDefault);
-  // A wavefront's row pipeline takes about 0.1 ms, so the fused sweep needs
-  // enough wavefronts to fill the GPU before it beats the single-step sweep
-  // (measured crossovers on MI355X: about 1000^2 nodes for F64, 1400^2 for
-  // F32S and 2300^2 for F16S/BF16S, whose single-step sweep moves the fewest
-  // bytes; below them the single-step sweep runs from the 256 MB last-level
-  // cache).
-  const int64_t min_items = (st == LB_F64) ? 300 : (st == LB_F32S) ? 600 : 1600;
-  return items >= min_items;
+  // With the row count chosen per lattice (fused_rows), fused launches beat
+  // single-step ones on MI355X from 64^2 nodes up in every storage format
+  // (1.1-1.3x at 64^2..192^2, 2-3x at 384^2..1024^2, 3.6x for F64 at
+  // 4096^2) and tie at 32^2.
+  return fused_levels(st) > 1 && (int64_t)nx * ny >= 48 * 48;
 }
 
 hipError_t launch_batched_fused(int eq, int st, const LatticeDesc* d, const int* item_map,

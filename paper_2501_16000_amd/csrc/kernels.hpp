@@ -38,13 +38,20 @@ bool fused_worthwhile(int st, int nx, int ny);
 hipError_t launch_fused_sweep(int eq, int coll, int bc, int st, const void* src, void* dst,
                               const Geometry& g, const Coef64& c, int rows, hipStream_t s);
 
-// Wavefronts of the fused sweep for storage st that the current device runs
-// at once (0 if the query fails).
-int fused_wave_slots(int st);
+// SIMDs of the current device and wavefronts of the fused sweep for storage
+// st that one SIMD holds at once (zeros if the query fails).
+struct FusedShape {
+  int simds;
+  int waves_per_simd;
+};
+FusedShape fused_shape(int st);
 
-// Output rows per wavefront of a fused launch on an nx x ny lattice, given
-// the device's wave slots.
-int fused_rows(int st, int nx, int ny, int slots);
+// Modelled time of one fused launch on an nx x ny lattice with H output rows
+// per wavefront, in row-collision units of one wavefront.
+double fused_cost(int st, int nx, int ny, int H, const FusedShape& sh);
+
+// Output rows per wavefront (a multiple of 3) that minimise fused_cost.
+int fused_rows(int st, int nx, int ny, const FusedShape& sh);
 
 // g from fields (device FP64 [ny][nx] each); counts invalid input nodes
 // (non-finite value or rho <= 0) into *bad.

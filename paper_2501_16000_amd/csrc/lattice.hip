@@ -243,7 +243,7 @@ lb_status lb_create_ex(const lb_options* opt, lb_lattice** out) {
   if (e != hipSuccess) return cleanup(hip_fail(nullptr, e, "hipMalloc(counter)"));
   if (fused_levels(h->opt.storage) > 1)
     h->fused_rows = fused_rows(h->opt.storage, h->geo.nx, h->geo.ny,
-                               fused_wave_slots(h->opt.storage));
+                               fused_shape(h->opt.storage));
   *out = h;
   return LB_OK;
 }

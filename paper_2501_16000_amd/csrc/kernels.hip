@@ -195,7 +195,8 @@ __global__ __launch_bounds__(SweepShape<ST>::BS) void sweep_kernel(
 // marches down H output rows; lane l holds column X0 - K + l.  The rows of
 // time level 0 come from memory; level k + 1 of row y is computed from the
 // last three rows of level k (a sliding window kept in registers), the x
-// neighbours arrive by one-lane DPP shifts.  Every level loses one lane on
+// neighbours arrive by one-lane shifts (DPP, or ds_bpermute for window rows
+// of the 16-bit formats).  Every level loses one lane on
 // each side, so the 64 - 2K middle lanes of level K are stored.  The rows
 // needed above and below the strip's H rows (K on each side) are recomputed
 // by the neighbouring strips.  Between levels the populations are rounded
@@ -241,11 +242,6 @@ __device__ __forceinline__ double from_right(double v) {
 // a value from the other edge; they are outside the valid region).
 __device__ __forceinline__ float lane_perm(float v, int src_byte) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(src_byte, __float_as_int(v)));
-}
-__device__ __forceinline__ double lane_perm(double v, int src_byte) {
-  const int lo = __double2loint(v), hi = __double2hiint(v);
-  return __hiloint2double(__builtin_amdgcn_ds_bpermute(src_byte, hi),
-                          __builtin_amdgcn_ds_bpermute(src_byte, lo));
 }
 
 // One wavefront's strip: K time steps over the rows Y0 .. Y0 + H - 1 of the

@@ -98,10 +98,12 @@ typedef struct lb_options {
                                  kept alive until lb_destroy returns           */
   int device;                 /* HIP device ordinal; -1: current device         */
   int check_nonfinite;        /* nonzero: lb_step scans for NaN/Inf afterwards  */
-  int fuse_steps;             /* 0: lb_step advances several time steps per
-                                 launch when the lattice is large enough for
-                                 that to be faster (register-resident
-                                 multi-step sweep; same result bit for bit);
+  int fuse_steps;             /* 0: lb_step advances six time steps per
+                                 launch (register-resident multi-step sweep;
+                                 same result bit for bit) on lattices of at
+                                 least 48^2 nodes, where it is faster, and
+                                 one step per launch below that and for the
+                                 remainder of n;
                                  1: one sweep launch per time step;
                                  2: fused launches (six steps each, every
                                  storage) whatever the size                    */

@@ -264,6 +264,20 @@ __device__ __forceinline__ void fused_strip(const typename Storage<ST>::T* __res
   // faster for F16S and 7 % for BF16S); F64 and F32S keep all shifts on DPP
   // (no gain there: F32S folds most DPP shifts into its arithmetic).
   constexpr bool PERM = ST == LB_F16S || ST == LB_BF16S;
+  // A window population as stored (pre-shifted with PERM) and as pulled at
+  // the gather (shifted there without PERM).
+  auto enter = [&](R v, int src_byte) -> R {
+    if constexpr (PERM) return lane_perm(v, src_byte);
+    else return v;
+  };
+  auto pull_left = [&](R v) -> R {
+    if constexpr (PERM) return v;
+    else return from_left(v);
+  };
+  auto pull_right = [&](R v) -> R {
+    if constexpr (PERM) return v;
+    else return from_right(v);
+  };
   const bool wall = BC == LB_BC_BOUNCEBACK && (col == 0 || col == nx - 1);
   // Window of level lv: row j of the level lives in slot j % 3 and holds
   // pops 0, 1, 2, 3, 5, 6 (pops 4, 7, 8 of a row are used as soon as it
@@ -319,21 +333,21 @@ __device__ __forceinline__ void fused_strip(const typename Storage<ST>::T* __res
       // PERM, pops 1, 3, 5 and 6 enter the window already shifted to the
       // lane that pulls them (they are read one and two steps later).
       Sl[lv][q][0] = C[0];
-      Sl[lv][q][1] = PERM ? lane_perm(C[1], left_byte) : C[1];
+      Sl[lv][q][1] = enter(C[1], left_byte);
       Sl[lv][q][2] = C[2];
-      Sl[lv][q][3] = PERM ? lane_perm(C[3], right_byte) : C[3];
-      Sl[lv][q][4] = PERM ? lane_perm(C[5], left_byte) : C[5];
-      Sl[lv][q][5] = PERM ? lane_perm(C[6], right_byte) : C[6];
+      Sl[lv][q][3] = enter(C[3], right_byte);
+      Sl[lv][q][4] = enter(C[5], left_byte);
+      Sl[lv][q][5] = enter(C[6], right_byte);
       if (lv >= NP) break;  // no rows of level lv + 1 yet
       R N[9];
       const R(&A)[6] = Sl[lv][qa];  // row j - 2 (pops 2, 5, 6 used)
       const R(&B)[6] = Sl[lv][qb];  // row j - 1 (pops 0, 1, 3 used)
       N[0] = B[0];
-      N[1] = PERM ? B[1] : from_left(B[1]);
-      N[3] = PERM ? B[3] : from_right(B[3]);
+      N[1] = pull_left(B[1]);
+      N[3] = pull_right(B[3]);
       N[2] = A[2];
-      N[5] = PERM ? A[4] : from_left(A[4]);
-      N[6] = PERM ? A[5] : from_right(A[5]);
+      N[5] = pull_left(A[4]);
+      N[6] = pull_right(A[5]);
       N[4] = C[4];
       N[7] = from_right(C[7]);
       N[8] = from_left(C[8]);

@@ -61,6 +61,18 @@ __device__ __forceinline__ int wrap_sub(int v, int c, int n) {
   return c == 0 ? v : (c > 0 ? wrap_dec(v, n) : wrap_inc(v, n));
 }
 
+// Workgroups go to the 8 XCDs of the chip round-robin (workgroup b to XCD
+// b mod 8), and each XCD has its own L2.  xcd_block() renumbers them (a
+// bijection on 0 .. gridDim.x - 1) so that every XCD takes one contiguous
+// range: neighbouring tiles, which share cache lines at their edges, run on
+// the same XCD.  Used by the fused sweeps, whose strips share 2K halo
+// columns (their HBM reads fell from 1.27-1.62 to 1.16-1.19 times the
+// algorithmic bytes).
+__device__ __forceinline__ int xcd_block() {
+  const int nwg = gridDim.x, b = blockIdx.x, xcd = b % 8, per = nwg / 8, extra = nwg % 8;
+  return xcd * per + (xcd < extra ? xcd : extra) + b / 8;
+}
+
 // ---------------------------------------------------------------- sweep --
 // Launch shape per storage: nodes per thread (VX) and workgroup size.  One
 // node per thread keeps the FP64 and FP32 collisions at high occupancy; two
@@ -168,6 +180,9 @@ __global__ __launch_bounds__(SweepShape<ST>::BS) void sweep_kernel(
   using S = Storage<ST>;
   using R = typename S::R;
   constexpr int VX = SweepShape<ST>::VX, BS = SweepShape<ST>::BS;
+  // Plain block order: renumbering the blocks per XCD (xcd_block) removed
+  // the 4 % of reads that straddle two blocks' x ranges but made this
+  // HBM-bound sweep 5 % slower (measured), so it is not used here.
   const int y = blockIdx.x / nseg;
   const int x0 = ((blockIdx.x - y * nseg) * BS + threadIdx.x) * VX;
   if (x0 >= g.nx) return;
@@ -388,9 +403,10 @@ __global__ __launch_bounds__(256) void fused_sweep_kernel(
     const typename Storage<ST>::T* __restrict__ src, typename Storage<ST>::T* __restrict__ dst,
     Geometry g, Coef64 c, int strips, int items, int H) {
   constexpr int W = 64 - 2 * K;
-  // The wavefront index is uniform: keep it (and every row base derived
-  // from it) in scalar registers.
-  const int wave = blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // Neighbouring strips share their halo columns, which then come from the
+  // XCD's L2 instead of HBM a second time.  The wavefront index is uniform:
+  // keep it (and every row base derived from it) in scalar registers.
+  const int wave = xcd_block() * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (wave >= items) return;  // whole wavefronts leave together
   const int strip = wave % strips, seg = wave / strips;
@@ -411,7 +427,7 @@ __global__ __launch_bounds__(256) void batched_fused_kernel(const LatticeDesc* _
   using S = Storage<ST>;
   using Tt = typename S::T;
   constexpr int W = 64 - 2 * KMAX;
-  const int64_t item = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t item = (int64_t)xcd_block() * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (item >= items) return;  // whole wavefronts leave together
   const LatticeDesc& L = d[map[item]];

@@ -163,19 +163,27 @@ def smooth_random_velocity(n: int, umax: float = 0.03, modes: int = 8, seed: int
     al = rng.uniform(0.0, 2.0 * np.pi, (modes, modes))
     be = rng.uniform(0.0, 2.0 * np.pi, (modes, modes))
     xs = np.arange(n, dtype=np.float64)
-    ux = np.zeros((n, n))
-    uy = np.zeros((n, n))
     kk = 2.0 * np.pi / n
-    for m in range(1, modes + 1):
-        sx = np.sin(kk * m * xs[None, :] + al[m - 1, :, None])  # [l, x]
-        cx = np.cos(kk * m * xs[None, :] + al[m - 1, :, None])
-        for l in range(1, modes + 1):
-            a = A[m - 1, l - 1] / (m * m + l * l)
-            sy = np.sin(kk * l * xs + be[m - 1, l - 1])
-            cy = np.cos(kk * l * xs + be[m - 1, l - 1])
-            # d/dy of sin(..x..) sin(..y..) and -d/dx of it
-            ux += a * (kk * l) * np.outer(cy, sx[l - 1])
-            uy -= a * (kk * m) * np.outer(sy, cx[l - 1])
+    m = np.arange(1, modes + 1, dtype=np.float64)
+    a = A / (m[:, None] ** 2 + m[None, :] ** 2)          # [m, l]
+    # sin(kk m x + al) = sin(kk m x) cos(al) + cos(kk m x) sin(al): every term
+    # is a product of a function of y and a function of x, so both velocity
+    # components are one [n, 2 modes^2] x [2 modes^2, n] product.
+    ph_x = kk * m[:, None] * xs[None, :]                  # [m, x]
+    sxm, cxm = np.sin(ph_x), np.cos(ph_x)
+    ph_y = kk * m[None, :, None] * xs[None, None, :] + be[:, :, None]   # [m, l, y]
+    sy, cy = np.sin(ph_y), np.cos(ph_y)
+    # u_x = d psi / dy = sum a (kk l) cos(kk l y + be) sin(kk m x + al)
+    wx = (a * kk * m[None, :])[:, :, None] * cy           # [m, l, y]
+    left_x = np.concatenate([(wx * np.cos(al)[:, :, None]).sum(1),
+                             (wx * np.sin(al)[:, :, None]).sum(1)])   # [2m, y]
+    ux = left_x.T @ np.concatenate([sxm, cxm])           # [y, x]
+    # u_y = -d psi / dx = -sum a (kk m) sin(kk l y + be) cos(kk m x + al),
+    # cos(kk m x + al) = cos(kk m x) cos(al) - sin(kk m x) sin(al)
+    wy = (a * kk * m[:, None])[:, :, None] * sy
+    left_y = np.concatenate([(wy * np.cos(al)[:, :, None]).sum(1),
+                             -(wy * np.sin(al)[:, :, None]).sum(1)])
+    uy = -(left_y.T @ np.concatenate([cxm, sxm]))
     speed = np.sqrt(ux * ux + uy * uy).max()
     scale = umax / speed
     return np.full((n, n), float(rho)), ux * scale, uy * scale

@@ -9,7 +9,8 @@ oracle and asserts the bound measured for it (with margin):
   * the periodic shocktube (16384 x 4, rho 1.5 | 0.75, tau = 0.55, 4000
     steps, rho0 = 1.125): y-averaged density profile, L2 and Linf;
   * the polynomial-equilibrium random smooth flow (512^2 stand-in of the
-    8192^2 workload, tau = 0.7, 500 steps): kinetic energy history.
+    8192^2 workload, tau = 0.7, 500 steps): kinetic energy history; and the
+    8192^2 workload itself against the GPU FP64 run.
 """
 import sys
 
@@ -165,3 +166,39 @@ def test_f64_kinetic_energy_matches_oracle():
         L.step(100)
         d = L.diagnostics()
     np.testing.assert_allclose(d[3], oracle.diagnostics(f, theta)[3], rtol=1e-12)
+
+
+# The full-size polynomial workload: 8192^2, tau = 0.7, 500 steps.  The
+# oracle cannot run it (33.6 G node updates), so the GPU FP64 run stands in
+# for it: the FP64 sweep equals the oracle element by element in the parity
+# tests (within 1e-12 after 100 steps, sampled at 4096^2 and 32768^2) and in
+# the kinetic energy above.  Over 500 steps the modes (at most 8 per axis on
+# 8192) lose only about 2e-3 of their energy, so the decay itself is an
+# ill-conditioned difference; both errors are reported.
+KE_BOUND_8192 = {"f32s": 3e-4, "f16s": 1e-3, "bf16s": 2e-3}
+
+
+def test_polynomial_random_flow_8192_full_size():
+    oreg = lib()
+    n, tau, theta, steps = 8192, 0.7, 1 / 3, 500
+    rho, ux, uy = workloads.smooth_random_velocity(n, umax=0.03, seed=2501)
+    ke = {}
+    for storage in ["f64"] + STORAGES:
+        say(f"[precision] poly2 random smooth flow 8192^2 {storage}")
+        with oreg.Lattice(n, n, tau, theta, equilibrium="poly2", storage=storage) as L:
+            L.init(rho, ux, uy)
+            h = [L.diagnostics()[3]]
+            for _ in range(5):
+                L.step(steps // 5)
+                h.append(L.diagnostics()[3])
+        ke[storage] = np.array(h)
+    ref = ke["f64"]
+    say(f"  FP64 kinetic energy {ref[0]:.6e} -> {ref[-1]:.6e} (decay {1 - ref[-1] / ref[0]:.3e})")
+    errs = {}
+    for storage in STORAGES:
+        errs[storage] = np.max(np.abs(ke[storage] - ref)) / ref[0]
+        decay_err = abs((ke[storage][-1] - ke[storage][0]) / (ref[-1] - ref[0]) - 1)
+        say(f"  {storage}: max |KE - KE_f64| / KE(0) {errs[storage]:.3e}; "
+            f"relative error of the KE decay {decay_err:.3e}")
+    for storage in STORAGES:
+        assert errs[storage] < KE_BOUND_8192[storage], storage

@@ -245,8 +245,10 @@ __host__ __device__ __forceinline__ void equilibrium(R drho, R rho, R ux, R uy, 
 // f^post_i = f^eq_i (1 + ax - by + tx Cy) (Eqs. 6, 7; the bracket terms are
 // defined in collide below), evaluated as
 //   rho X (Y (1 - by) + Y ax + (Y Cy) tx)                  (unshifted), or
-//   deq_i + rho X (Y ax - Y by + (Y Cy) tx)                 (shifted),
-// with the per-y products formed once: three operations per population.
+//   deq_i + rho X (Y ax - Y by + (Y Cy) tx)                 (shifted, with
+//   deq_i = f^eq_i - w_i rho0 folded in: see below),
+// with the per-x and per-y products formed once: three operations per
+// population.
 // d13 = f1 + f3 - f2 - f4 and d57 = f5 + f7 - f6 - f8 (second moments).
 template <bool SHIFTED, typename R>
 __host__ __device__ __forceinline__ void collide_guided_oreg(R (&f)[9], const Coeffs<R>& k, R drho,
@@ -254,7 +256,8 @@ __host__ __device__ __forceinline__ void collide_guided_oreg(R (&f)[9], const Co
                                                              R uyy, R d13, R d57) {
 #pragma clang fp contract(off)
   R Xm, X0, Xp, Ym, Y0, Yp;
-  R deq[9];
+  // Shifted storage only: E = drho X + rho0 dX (per x) and (rho0 a) dY.
+  R Exm = 0, Ex0 = 0, Exp = 0, a0dYm = 0, a0dY0 = 0, a0dYp = 0, a1dYm = 0, a1dY0 = 0, a1dYp = 0;
   if constexpr (!SHIFTED) {
     // Psi(+-1) = (a1 + u^2/2) +- u/2, Psi(0) = a0 - u^2.
     const R gx = fmadd(R(0.5), uxx, k.a1), gy = fmadd(R(0.5), uyy, k.a1);
@@ -268,15 +271,10 @@ __host__ __device__ __forceinline__ void collide_guided_oreg(R (&f)[9], const Co
     const R dYm = fmadd(R(-0.5), uy, hy), dY0 = -uyy, dYp = fmadd(R(0.5), uy, hy);
     Xm = k.a1 + dXm, X0 = k.a0 + dX0, Xp = k.a1 + dXp;
     Ym = k.a1 + dYm, Y0 = k.a0 + dY0, Yp = k.a1 + dYp;
-    const R Exm = fmadd(drho, Xm, k.rho0 * dXm), Ex0 = fmadd(drho, X0, k.rho0 * dX0),
-            Exp = fmadd(drho, Xp, k.rho0 * dXp);
-    const R a0dYm = k.r0a0 * dYm, a0dY0 = k.r0a0 * dY0, a0dYp = k.r0a0 * dYp;
-    const R a1dYm = k.r0a1 * dYm, a1dY0 = k.r0a1 * dY0, a1dYp = k.r0a1 * dYp;
-    unroll<0, 9>([&](auto I) {
-      constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
-      const R adY = (cx == 0) ? pick<cy>(a0dYm, a0dY0, a0dYp) : pick<cy>(a1dYm, a1dY0, a1dYp);
-      deq[I.value] = fmadd(pick<cx>(Exm, Ex0, Exp), pick<cy>(Ym, Y0, Yp), adY);
-    });
+    Exm = fmadd(drho, Xm, k.rho0 * dXm), Ex0 = fmadd(drho, X0, k.rho0 * dX0),
+    Exp = fmadd(drho, Xp, k.rho0 * dXp);
+    a0dYm = k.r0a0 * dYm, a0dY0 = k.r0a0 * dY0, a0dYp = k.r0a0 * dYp;
+    a1dYm = k.r0a1 * dYm, a1dY0 = k.r0a1 * dY0, a1dYp = k.r0a1 * dYp;
   }
   const R rXm = rho * Xm, rX0 = rho * X0, rXp = rho * Xp;
   // Non-equilibrium stress (2 s = Pi_xx - Pi_yy, S_xy) and the bracket of
@@ -300,13 +298,18 @@ __host__ __device__ __forceinline__ void collide_guided_oreg(R (&f)[9], const Co
       f[I.value] = pick<cx>(rXm, rX0, rXp) * v;
     });
   } else {
+    // deq_i + rho X (Y ax - Y by + (Y Cy) tx)
+    //   = Y (E + rho X ax) + (rho X tx) (Y Cy) + ((rho0 ax) dY - rho X (Y by)),
+    // every term of the size of the deviation.
     const R Bm = Ym * bym, B0 = Y0 * by0, Bp = Yp * byp;
+    const R Gm = fmadd(rXm, axm, Exm), G0 = fmadd(rX0, ax0, Ex0), Gp = fmadd(rXp, axp, Exp);
+    const R Tm = rXm * txm, T0 = rX0 * tx0, Tp = rXp * txp;
     unroll<0, 9>([&](auto I) {
       constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
-      const R Y = pick<cy>(Ym, Y0, Yp);
-      const R v = fmadd(pick<cy>(Qm, Q0, Qp), pick<cx>(txm, tx0, txp),
-                        fmadd(Y, pick<cx>(axm, ax0, axp), -pick<cy>(Bm, B0, Bp)));
-      f[I.value] = fmadd(pick<cx>(rXm, rX0, rXp), v, deq[I.value]);
+      const R adY = (cx == 0) ? pick<cy>(a0dYm, a0dY0, a0dYp) : pick<cy>(a1dYm, a1dY0, a1dYp);
+      const R r = fmadd(-pick<cx>(rXm, rX0, rXp), pick<cy>(Bm, B0, Bp), adY);
+      f[I.value] = fmadd(pick<cy>(Ym, Y0, Yp), pick<cx>(Gm, G0, Gp),
+                         fmadd(pick<cx>(Tm, T0, Tp), pick<cy>(Qm, Q0, Qp), r));
     });
   }
 }

@@ -55,7 +55,7 @@ def parse():
     p.add_argument("--storage", default="f64", choices=sorted(BYTES_PER_NODE))
     p.add_argument("--variants", default="f32s,f16s,bf16s",
                    help="other storages to time on the same workload ('' for none)")
-    p.add_argument("--variant-steps", type=int, default=300)
+    p.add_argument("--variant-steps", type=int, default=600)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-steps", type=int, default=60,
                    help="oracle steps on the full lattice for the CPU baseline")
@@ -443,14 +443,16 @@ def main():
     repeats = {"n": 5, "steps": 300, "median": round(reps[2], 1), "min": round(reps[0], 1),
                "max": round(reps[-1], 1), "unit": "MLUPS"}
 
-    # the other relaxation times of the workload (same kernels, same work)
+    # the other relaxation times of the workload (same kernels, same work,
+    # the same step count)
     tau_sweep = {}
     for t_other in (0.51, 1.0):
-        tms, tdiag = time_lattice(oreg, torch, n, t_other, args.storage, 300, args.warmup, fields)
+        tms, tdiag = time_lattice(oreg, torch, n, t_other, args.storage, args.steps, args.warmup,
+                                  fields)
         if tdiag[5] != 0:
             raise RuntimeError(f"non-finite populations at tau={t_other}")
-        tau_sweep[str(t_other)] = {"value": round(cells * 300 / (tms / 1e3) / 1e6, 1),
-                                   "unit": "MLUPS", "steps": 300}
+        tau_sweep[str(t_other)] = {"value": round(cells * args.steps / (tms / 1e3) / 1e6, 1),
+                                   "unit": "MLUPS", "steps": args.steps}
 
     variants = {}
     for st in [s for s in args.variants.split(",") if s and s != args.storage]:

@@ -255,8 +255,8 @@ __host__ __device__ __forceinline__ void equilibrium(R drho, R rho, R ux, R uy, 
 // d13 = f1 + f3 - f2 - f4 and d57 = f5 + f7 - f6 - f8 (second moments).
 template <bool SHIFTED, typename R>
 __host__ __device__ __forceinline__ void collide_guided_oreg(R (&f)[9], const Coeffs<R>& k, R drho,
-                                                             R rho, R inv, R ux, R uy, R uxx,
-                                                             R uyy, R d13, R d57) {
+                                                             R rho, R inv, R jx, R ux, R uy,
+                                                             R uxx, R uyy, R d13, R d57) {
 #pragma clang fp contract(off)
   R Xm, X0, Xp, Ym, Y0, Yp;
   // Shifted storage only: E = drho X + rho0 dX (per x) and (rho0 a) dY.
@@ -283,15 +283,19 @@ __host__ __device__ __forceinline__ void collide_guided_oreg(R (&f)[9], const Co
   const R rXm = rho * Xm, rX0 = rho * X0, rXp = rho * Xp;
   // Non-equilibrium stress (2 s = Pi_xx - Pi_yy, S_xy) and the bracket of
   // Eq. (6): kappa [..] = ks Cx^2 - ks Cy^2 + (kt Cx) Cy, C = c_i - u.
+  // (rho ux uy = jx uy.)
   const R s2 = fmadd(-rho, uxx - uyy, d13);
-  const R sxy = fmadd(-rho, ux * uy, d57);
+  const R sxy = fmadd(-jx, uy, d57);
   const R ks = (k.kappa_h * inv) * s2, kt = (k.kappa_2 * inv) * sxy;
-  const R Cxm = R(-1) - ux, Cx0 = -ux, Cxp = R(1) - ux;
-  const R Cym = R(-1) - uy, Cy0 = -uy, Cyp = R(1) - uy;
-  const R axm = (ks * Cxm) * Cxm, ax0 = ks * uxx, axp = (ks * Cxp) * Cxp;
-  const R bym = (ks * Cym) * Cym, by0 = ks * uyy, byp = (ks * Cyp) * Cyp;
-  const R txm = kt * Cxm, tx0 = kt * Cx0, txp = kt * Cxp;
-  const R Qm = Ym * Cym, Q0 = Y0 * Cy0, Qp = Yp * Cyp;  // Y Cy
+  // With C = -1 - u, -u, 1 - u:  ks C^2 = ks (1 + u^2) +- 2 ks u, ks u^2;
+  // kt C = -kt - kt u, -kt u, kt - kt u;  Y C = -(Y + Y u), -Y u, Y - Y u.
+  const R ksx = ks * ux, kox = ks * (R(1) + uxx);
+  const R axm = fmadd(R(2), ksx, kox), ax0 = ks * uxx, axp = fmadd(R(-2), ksx, kox);
+  const R ksy = ks * uy, koy = ks * (R(1) + uyy);
+  const R bym = fmadd(R(2), ksy, koy), by0 = ks * uyy, byp = fmadd(R(-2), ksy, koy);
+  const R ktx = kt * ux;
+  const R txm = -kt - ktx, tx0 = -ktx, txp = kt - ktx;
+  const R Qm = fmadd(-Ym, uy, -Ym), Q0 = -(Y0 * uy), Qp = fmadd(-Yp, uy, Yp);  // Y Cy
   if constexpr (!SHIFTED) {
     const R Pm = fmadd(-Ym, bym, Ym), P0 = fmadd(-Y0, by0, Y0), Pp = fmadd(-Yp, byp, Yp);
     unroll<0, 9>([&](auto I) {
@@ -335,7 +339,7 @@ __host__ __device__ __forceinline__ void collide(R (&f)[9], const Coeffs<R>& k) 
   const R uxx = ux * ux, uyy = uy * uy;
 
   if constexpr (EQ == LB_EQ_GUIDED && COLL == LB_COLL_OREG) {
-    collide_guided_oreg<SHIFTED>(f, k, drho, rho, inv, ux, uy, uxx, uyy, s13 - s24, s57 - s68);
+    collide_guided_oreg<SHIFTED>(f, k, drho, rho, inv, jx, ux, uy, uxx, uyy, s13 - s24, s57 - s68);
     return;
   }
 

@@ -63,6 +63,16 @@ CASES = [
     (37, 53, "poly2", 1 / 3, 0.6, "bgk", "periodic"),
     (40, 3, "guided", 0.35, 0.7, "oreg", "bounceback"),
     (800, 1, "guided", 0.4, 0.6, "oreg", "bounceback"),
+    # the default lb_step path fuses six steps per launch from 48^2 nodes up,
+    # with the row block chosen per lattice: both sides of the threshold,
+    # narrow-tall and wide-short strips, every collision and boundary
+    (48, 48, "guided", 1 / 3, 0.8, "oreg", "periodic"),
+    (47, 49, "guided", 1 / 3, 0.8, "oreg", "periodic"),
+    (52, 700, "guided", 0.35, 0.6, "oreg", "periodic"),
+    (3000, 49, "guided", 1 / 3, 0.51, "oreg", "periodic"),
+    (200, 200, "poly2", 1 / 3, 0.7, "oreg", "periodic"),
+    (64, 64, "guided", 0.4, 0.9, "bgk", "periodic"),
+    (100, 60, "guided", 1 / 3, 0.6, "oreg", "bounceback"),
 ]
 
 

@@ -363,6 +363,12 @@ FUSED_CASES = [
     (52, 300, "guided", 1 / 3, 0.7, "oreg", "periodic", "f64"),
     (52, 198, "guided", 0.35, 0.6, "oreg", "periodic", "f32s"),
     (60, 500, "guided", 1 / 3, 0.55, "oreg", "periodic", "bf16s"),
+    # F32S: strip edges across the periodic wrap, walls, BGK, degenerate shapes
+    (117, 40, "guided", 1 / 3, 0.6, "oreg", "periodic", "f32s"),
+    (116, 70, "guided", 0.35, 0.7, "oreg", "bounceback", "f32s"),
+    (233, 35, "poly2", 1 / 3, 0.8, "bgk", "periodic", "f32s"),
+    (1, 200, "guided", 1 / 3, 0.53, "oreg", "periodic", "f32s"),
+    (801, 1, "guided", 0.4, 0.6, "oreg", "bounceback", "f32s"),
 ]
 
 

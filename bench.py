@@ -401,7 +401,8 @@ def main():
     if K > 1:
         # the dominant kernel: K steps per launch; time whole launches only
         nl = max(1, args.steps // K)
-        fms, _ = time_lattice(oreg, torch, n, tau, args.storage, nl * K, K, fields)
+        warm = max(K, (args.warmup + K - 1) // K * K)  # whole launches, as many as the main run
+        fms, _ = time_lattice(oreg, torch, n, tau, args.storage, nl * K, warm, fields)
         per_launch_s = fms / 1e3 / nl
         flops = FLOPS_PER_UPDATE * K * cells
         peak = FP64_PEAK_TFLOPS if args.storage == "f64" else FP32_PEAK_TFLOPS

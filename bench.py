@@ -155,7 +155,32 @@ def time_box(oreg3, torch, n, tau, storage, steps, warmup, fields):
     return ms, diag
 
 
-def d3q27_bench(torch, n, tau, steps):
+def copy_ceiling(oreg, torch, nbytes, reps=20):
+    """GB/s of the library's plain streaming copy (lb_copy_device: every byte
+    read once and written once) between two device buffers of nbytes, timed
+    with HIP events on its stream: the practical HBM ceiling."""
+    stream = torch.cuda.Stream()  # default priority
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    h = stream.cuda_stream
+    for _ in range(3):
+        oreg.copy_device(src.data_ptr(), dst.data_ptr(), nbytes, h)
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for _ in range(reps):
+        oreg.copy_device(src.data_ptr(), dst.data_ptr(), nbytes, h)
+    end.record(stream)
+    torch.cuda.synchronize()
+    if not bool((dst[:: max(1, nbytes // 4096)] == 1).all()):
+        raise RuntimeError("lb_copy_device did not copy")
+    gbs = 2.0 * nbytes * reps / (start.elapsed_time(end) / 1e3) / 1e9
+    del src, dst
+    return gbs
+
+
+def d3q27_bench(torch, n, tau, steps, copy_gbs=None):
     """The D3Q27 sweep (one launch per step) on an n^3 box, every storage."""
     from paper_2501_16000_amd import oreg3, workloads
     fields = workloads.shear_wave3(n, 0.05)
@@ -175,6 +200,8 @@ def d3q27_bench(torch, n, tau, steps):
                                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                                 "traffic": load_traffic(st, n, alg, d3=True),
                                 "algorithmic_bytes_per_launch": alg}}
+        if copy_gbs:
+            out[st]["roofline"]["frac_of_copy"] = round(ach / copy_gbs, 4)
     return out
 
 
@@ -446,6 +473,13 @@ def main():
                            "unit": "GB/s", "frac": round(s_ach / HBM_PEAK_GBS, 4),
                            "traffic": load_traffic(args.storage, n, alg_bytes),
                            "algorithmic_bytes_per_launch": alg_bytes}}
+    # the practical ceiling: a plain copy of one population buffer of this
+    # lattice (each byte read once and written once, as one sweep step does)
+    copy_bytes = alg_bytes // 2 // 16 * 16
+    copy_gbs = copy_ceiling(oreg, torch, copy_bytes)
+    copy = {"value": round(copy_gbs, 1), "unit": "GB/s", "kernel": "copy_kernel (lb_copy_device)",
+            "bytes_per_copy": copy_bytes, "copies": 20}
+    single["roofline"]["frac_of_copy"] = round(s_ach / copy_gbs, 4)
 
     # spread: five more timed runs of 300 steps each
     reps = []
@@ -513,11 +547,12 @@ def main():
         "roofline": roofline,
         "repeats": repeats,
         "single_step": single,
+        "copy_ceiling": copy,
         "tau_sweep": tau_sweep,
         "variants": variants,
     }
     if args.d3q27_n > 0:
-        line["d3q27"] = d3q27_bench(torch, args.d3q27_n, tau, args.d3q27_steps)
+        line["d3q27"] = d3q27_bench(torch, args.d3q27_n, tau, args.d3q27_steps, copy_gbs)
     if args.serving_requests > 0:
         line["serving"] = serving_bench(oreg, args.serving_requests, args.serving_plain_sample)
     if not args.no_cpu_baseline:

@@ -192,6 +192,17 @@ int64_t lb_device_bytes(const lb_lattice* h);
    NULL-safe (returns LB_OK). */
 lb_status lb_destroy(lb_lattice* h);
 
+/* Measurement helper, not a step of the method: copy `bytes` bytes from src
+   to dst (caller-owned device memory of the current device, 16-byte
+   aligned, not overlapping) with a plain streaming kernel, every byte read
+   once and written once, enqueued on hip_stream (NULL: the null stream) and
+   asynchronous.  Timed by the caller, it gives the practical HBM ceiling
+   that the sweeps' achieved bandwidth is set against.  LB_EINVAL for a NULL
+   buffer, a size that is negative or not a multiple of 16, misaligned or
+   overlapping buffers; LB_EDEVICE (or LB_ENOMEM) if the launch fails.
+   bytes == 0 is a no-op. */
+lb_status lb_copy_device(const void* src, void* dst, int64_t bytes, void* hip_stream);
+
 /* Static text for a status code. */
 const char* lb_status_string(lb_status s);
 

@@ -16,7 +16,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liboreg.so")
-SOURCES = ["lattice.hip", "kernels.hip", "serve.hip", "lattice3.hip", "kernels3.hip"]
+SOURCES = ["lattice.hip", "kernels.hip", "serve.hip", "lattice3.hip", "kernels3.hip", "copy.hip"]
 
 ARCH = "gfx950"
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.

@@ -116,4 +116,7 @@ int fused_strip_width(int st);
 hipError_t launch_batched_fused(int eq, int st, const LatticeDesc* d, const int* item_map,
                                 int64_t items, int64_t T, hipStream_t s);
 
+// Plain streaming copy of bytes / 16 16-byte words (copy.hip).
+hipError_t launch_copy(const void* src, void* dst, int64_t bytes, hipStream_t s);
+
 }  // namespace oreg

@@ -4,6 +4,7 @@
 
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -464,6 +465,22 @@ lb_status lb_destroy(lb_lattice* h) {
   }
   delete h;
   return st;
+}
+
+lb_status lb_copy_device(const void* src, void* dst, int64_t bytes, void* hip_stream) {
+  if (!src || !dst) return fail(nullptr, LB_EINVAL, "lb_copy_device: NULL buffer");
+  if (bytes < 0 || bytes % 16 != 0)
+    return fail(nullptr, LB_EINVAL, "lb_copy_device: %lld bytes is not a multiple of 16",
+                (long long)bytes);
+  const uintptr_t a = reinterpret_cast<uintptr_t>(src), b = reinterpret_cast<uintptr_t>(dst);
+  if ((a | b) % 16 != 0)
+    return fail(nullptr, LB_EINVAL, "lb_copy_device: buffers must be 16-byte aligned");
+  if (bytes > 0 && a < b + (uintptr_t)bytes && b < a + (uintptr_t)bytes)
+    return fail(nullptr, LB_EINVAL, "lb_copy_device: buffers overlap");
+  if (bytes == 0) return LB_OK;
+  const hipError_t e = launch_copy(src, dst, bytes, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(nullptr, e, "copy_kernel launch");
+  return LB_OK;
 }
 
 const char* lb_status_string(lb_status s) {

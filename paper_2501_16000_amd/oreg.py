@@ -97,12 +97,13 @@ lb_device_bytes = _sig("lb_device_bytes", ctypes.c_int64, [_H])
 lb_destroy = _sig("lb_destroy", ctypes.c_int, [_H])
 lb_status_string = _sig("lb_status_string", ctypes.c_char_p, [ctypes.c_int])
 lb_last_error = _sig("lb_last_error", ctypes.c_char_p, [_H])
+lb_copy_device = _sig("lb_copy_device", ctypes.c_int, [_VP, _VP, ctypes.c_int64, _VP])
 
 EXPORTED = [
     "lb_options_init", "lb_create", "lb_create_ex", "lb_init", "lb_init_device", "lb_step",
     "lb_moments", "lb_moments_device", "lb_populations", "lb_set_populations",
     "lb_diagnostics", "lb_density_profile", "lb_sync", "lb_time", "lb_get_options",
-    "lb_device_bytes", "lb_destroy", "lb_status_string", "lb_last_error",
+    "lb_device_bytes", "lb_destroy", "lb_status_string", "lb_last_error", "lb_copy_device",
 ]
 
 
@@ -117,6 +118,13 @@ class LBError(RuntimeError):
 def check(status: int, handle=None) -> None:
     if status != LB_OK:
         raise LBError(status, (lb_last_error(handle) or b"").decode())
+
+
+def copy_device(src_ptr: int, dst_ptr: int, nbytes: int, stream: int = 0) -> None:
+    """``lb_copy_device``: the plain streaming copy between two device buffers
+    (the practical HBM ceiling); asynchronous on ``stream`` (a HIP stream
+    handle, 0 for the null stream)."""
+    check(lb_copy_device(src_ptr, dst_ptr, nbytes, stream or None))
 
 
 def _ptr(a: np.ndarray):

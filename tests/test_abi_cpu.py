@@ -96,6 +96,21 @@ def test_null_arguments():
     assert m.lb_device_bytes(None) == 0
 
 
+def test_copy_device_validates_before_any_device_call():
+    """The measurement copy rejects bad arguments on the host (no buffer is
+    touched: the addresses below are never dereferenced)."""
+    m = oreg()
+    a, b = 1 << 20, 1 << 24
+    assert m.lb_copy_device(None, b, 16, None) == m.LB_EINVAL
+    assert m.lb_copy_device(a, None, 16, None) == m.LB_EINVAL
+    assert m.lb_copy_device(a, b, -16, None) == m.LB_EINVAL
+    assert m.lb_copy_device(a, b, 24, None) == m.LB_EINVAL          # not a multiple of 16
+    assert m.lb_copy_device(a + 8, b, 16, None) == m.LB_EINVAL      # misaligned
+    assert m.lb_copy_device(a, a + 64, 128, None) == m.LB_EINVAL    # overlapping
+    assert "overlap" in m.lb_last_error(None).decode()
+    assert m.lb_copy_device(a, b, 0, None) == m.LB_OK               # nothing to do
+
+
 def test_status_strings():
     m = oreg()
     for code in (m.LB_OK, m.LB_EINVAL, m.LB_ENOMEM, m.LB_EDEVICE, m.LB_ESTATE, m.LB_ENONFINITE,

@@ -390,3 +390,22 @@ def test_fused_steps_equal_single_steps(nx, ny, eq, theta, tau, coll, bc, storag
     if storage == "f64":
         ref = oracle.run(f0, 37, tau, theta, eq, collision=coll, bc_x=bc)
         assert rel_err(out[0], ref) <= RTOL
+
+
+@pytest.mark.parametrize("nbytes", [16, 4096 + 48, (1 << 26) + 16 * 7])
+def test_copy_device_copies_every_byte(nbytes):
+    """lb_copy_device (the bandwidth reference of the benchmark) copies the
+    bytes it is given and nothing past them."""
+    import torch
+    oreg = lib()
+    say(f"[copy] {nbytes} bytes")
+    g = torch.Generator(device="cpu").manual_seed(nbytes)
+    host = torch.randint(0, 256, (nbytes + 64,), dtype=torch.uint8, generator=g)
+    src = host.to("cuda")
+    dst = torch.zeros(nbytes + 64, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    oreg.copy_device(src.data_ptr(), dst.data_ptr(), nbytes, stream)
+    torch.cuda.synchronize()
+    out = dst.cpu()
+    assert torch.equal(out[:nbytes], host[:nbytes])
+    assert int(out[nbytes:].count_nonzero()) == 0

@@ -206,13 +206,14 @@ __global__ __launch_bounds__(SweepShape<ST>::BS) void sweep_kernel(
 }
 
 // ------------------------------------------------ multi-step (fused) sweep --
-// K time steps per launch.  Each wavefront owns a strip of 64 columns and
-// marches down H output rows; lane l holds column X0 - K + l.  The rows of
+// K time steps per launch.  Each wavefront owns a strip of 64 columns (in
+// F32S each workgroup one of 256, see fused_strip) and marches down H output
+// rows; lane l holds column X0 - K + l.  The rows of
 // time level 0 come from memory; level k + 1 of row y is computed from the
 // last three rows of level k (a sliding window kept in registers), the x
 // neighbours arrive by one-lane shifts (DPP, or ds_bpermute for window rows
-// of the 16-bit formats).  Every level loses one lane on
-// each side, so the 64 - 2K middle lanes of level K are stored.  The rows
+// of the 16-bit formats).  Every level loses one column on
+// each side, so the 64 - 2K (256 - 2K) middle columns of level K are stored.  The rows
 // needed above and below the strip's H rows (K on each side) are recomputed
 // by the neighbouring strips.  Between levels the populations are rounded
 // through the storage format, so the result equals K single-step sweeps bit
@@ -222,11 +223,14 @@ __global__ __launch_bounds__(SweepShape<ST>::BS) void sweep_kernel(
 // multiple of 3 chosen per lattice (fused_rows).
 constexpr int kFusedRowsDefault = 66;  // output rows per wavefront of fused_sweep_kernel
 
-// Fused levels per storage (every format fuses six steps; the specialisations
-// keep the choice per format explicit).
-template <int ST> struct FusedLevels { static constexpr int K = 6; };
-template <> struct FusedLevels<LB_F16S> { static constexpr int K = 6; };
-template <> struct FusedLevels<LB_BF16S> { static constexpr int K = 6; };
+// Fused launches per storage.  K: steps per launch (six in every format).
+// NW: wavefronts per strip.  F32S shares one
+// 256-column strip per workgroup (measured 9 % faster than a strip per
+// wavefront: 12 % fewer instructions per node update against six workgroup
+// barriers per row step); in F64 the same layout measured 2 % slower, and
+// the 16-bit formats pre-shift their windows inside the wavefront.
+template <int ST> struct FusedLevels { static constexpr int K = 6, NW = 1; };
+template <> struct FusedLevels<LB_F32S> { static constexpr int K = 6, NW = 4; };
 
 // lane l <- lane l - 1 (wave_shr:1) and lane l <- lane l + 1 (wave_shl:1).
 // Lanes without a source are outside the valid region of the next level: in
@@ -250,6 +254,28 @@ __device__ __forceinline__ double from_right(double v) {
                           __builtin_amdgcn_update_dpp(lo, lo, 0x130, 0xF, 0xF, false));
 }
 
+// The same shifts, with lane 0 (from_left_or) or lane 63 (from_right_or)
+// taking `e` instead: the value of the column beyond the wavefront's edge,
+// handed over by the neighbouring wavefront of the workgroup.
+__device__ __forceinline__ float from_left_or(float v, float e) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(e), __float_as_int(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float from_right_or(float v, float e) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(__float_as_int(e), __float_as_int(v), 0x130, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double from_left_or(double v, double e) {
+  return __hiloint2double(
+      __builtin_amdgcn_update_dpp(__double2hiint(e), __double2hiint(v), 0x138, 0xF, 0xF, false),
+      __builtin_amdgcn_update_dpp(__double2loint(e), __double2loint(v), 0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double from_right_or(double v, double e) {
+  return __hiloint2double(
+      __builtin_amdgcn_update_dpp(__double2hiint(e), __double2hiint(v), 0x130, 0xF, 0xF, false),
+      __builtin_amdgcn_update_dpp(__double2loint(e), __double2loint(v), 0x130, 0xF, 0xF, false));
+}
+
 // The same shifts through the LDS crossbar (ds_bpermute: no LDS memory, no
 // VALU issue slot), for values that are needed a step after they are
 // shifted: the latency is hidden and the VALU keeps its slots for the
@@ -259,26 +285,34 @@ __device__ __forceinline__ float lane_perm(float v, int src_byte) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(src_byte, __float_as_int(v)));
 }
 
-// One wavefront's strip: K time steps over the rows Y0 .. Y0 + H - 1 of the
-// columns X0 .. X0 + 63 - 2 KS (lane l holds column X0 - KS + l; KS >= K is
-// the strip's halo width, so lanes KS .. 63 - KS are stored).
-template <int K, int KS, int EQ, int COLL, int BC, int ST>
+// One strip: K time steps over the rows Y0 .. Y0 + H - 1 of the columns
+// X0 .. X0 + 64 NW - 1 - 2 KS.  Lane l of wavefront w holds column
+// X0 - KS + 64 w + l; KS >= K is the strip's halo width, so strip columns
+// KS .. 64 NW - 1 - KS are stored.  NW = 1: one wavefront per strip.  NW = 4
+// (SHARE): the four wavefronts of a workgroup sweep one 256-column strip
+// together and hand each other the populations that cross their edges
+// through LDS, so only the workgroup's outer edges carry a halo.
+template <int K, int KS, int EQ, int COLL, int BC, int ST, bool SHARE = false>
 __device__ __forceinline__ void fused_strip(const typename Storage<ST>::T* __restrict__ src,
                                             typename Storage<ST>::T* __restrict__ dst, int nx,
                                             int ny, int64_t P, int X0, int Y0, int H,
-                                            const Coeffs<typename Storage<ST>::R>& k, int lane) {
+                                            const Coeffs<typename Storage<ST>::R>& k, int lane,
+                                            int wv = 0) {
   using S = Storage<ST>;
   using R = typename S::R;
   using Tt = typename S::T;
+  constexpr int NW = SHARE ? 4 : 1;
   const int J = H + 2 * K;  // rows of level 0 read (H is a multiple of 3)
-  int col = (X0 - KS + lane) % nx;
+  const int cs = 64 * wv + lane;  // column within the strip, halo included
+  int col = (X0 - KS + cs) % nx;
   if (col < 0) col += nx;
-  const bool store_lane = lane >= KS && lane < 64 - KS && X0 - KS + lane < nx;
+  const bool store_lane = cs >= KS && cs < 64 * NW - KS && X0 - KS + cs < nx;
   const int left_byte = ((lane - 1) & 63) << 2, right_byte = ((lane + 1) & 63) << 2;
   // Window shifts through ds_bpermute for the 16-bit formats (measured 16 %
   // faster for F16S and 7 % for BF16S); F64 and F32S keep all shifts on DPP
-  // (no gain there: F32S folds most DPP shifts into its arithmetic).
+  // (no gain there).
   constexpr bool PERM = ST == LB_F16S || ST == LB_BF16S;
+  static_assert(!(SHARE && PERM), "pre-shifted windows take their edge values in-wave");
   // A window population as stored (pre-shifted with PERM) and as pulled at
   // the gather (shifted there without PERM).
   auto enter = [&](R v, int src_byte) -> R {
@@ -301,6 +335,31 @@ __device__ __forceinline__ void fused_strip(const typename Storage<ST>::T* __res
   // roles are compile-time constants and the window slides without register
   // moves.
   R Sl[K][3][6];
+  // Edge exchange (SHARE): edge[lv][q][e][w] holds pops 1, 5, 8, 3, 6, 7 of
+  // the row of level lv in ring slot q at the left (e = 0: lane 0) or right
+  // (e = 1: lane 63) edge of wavefront w.  Lane 0 of w pulls pops 1, 5, 8 from
+  // the right edge of w - 1, lane 63 pops 3, 6, 7 from the left edge of w + 1.
+  // A row is published when it arrives at its level; the barrier after each
+  // publication orders it before the other wavefronts' reads, and a slot is
+  // rewritten three rows later, after the barriers of the steps that read it.
+  __shared__ R edge[SHARE ? K : 1][3][2][4][6];
+  const bool at_edge = lane == 0 || lane == 63;
+  const int side = lane == 63 ? 1 : 0;
+  const int wl = (wv + 3) & 3, wr = (wv + 1) & 3;  // neighbours (wrapped ones feed halo lanes)
+  auto publish = [&](int lv, int q, const R(&v)[9]) {
+    if constexpr (SHARE) {
+      if (at_edge) {
+        R* e = edge[lv][q][side][wv];
+        e[0] = v[1];
+        e[1] = v[5];
+        e[2] = v[8];
+        e[3] = v[3];
+        e[4] = v[6];
+        e[5] = v[7];
+      }
+      __syncthreads();
+    }
+  };
   int row = (Y0 - K) % ny;
   if (row < 0) row += ny;
   Tt nb[3][9];  // level-0 rows: row j is loaded into nb[j % 3] one row ahead
@@ -336,6 +395,7 @@ __device__ __forceinline__ void fused_strip(const typename Storage<ST>::T* __res
     __asm__ volatile("" : "+v"(C[0]), "+v"(C[1]), "+v"(C[2]), "+v"(C[3]), "+v"(C[4]), "+v"(C[5]),
                      "+v"(C[6]), "+v"(C[7]), "+v"(C[8]));
     if constexpr (NP == K) store_row(Y0 + j - 1 - 2 * K);  // the previous step's output row
+    publish(0, q, C);
     // Prefetch the next row of level 0.  The last step reloads its own row
     // (a cache hit) instead of skipping the load: an unconditional load
     // leaves nothing of the old buffer alive.
@@ -358,14 +418,23 @@ __device__ __forceinline__ void fused_strip(const typename Storage<ST>::T* __res
       const R(&A)[6] = Sl[lv][qa];  // row j - 2 (pops 2, 5, 6 used)
       const R(&B)[6] = Sl[lv][qb];  // row j - 1 (pops 0, 1, 3 used)
       N[0] = B[0];
-      N[1] = pull_left(B[1]);
-      N[3] = pull_right(B[3]);
       N[2] = A[2];
-      N[5] = pull_left(A[4]);
-      N[6] = pull_right(A[5]);
       N[4] = C[4];
-      N[7] = from_right(C[7]);
-      N[8] = from_left(C[8]);
+      if constexpr (SHARE) {
+        N[1] = from_left_or(B[1], edge[lv][qb][1][wl][0]);
+        N[5] = from_left_or(A[4], edge[lv][qa][1][wl][1]);
+        N[8] = from_left_or(C[8], edge[lv][q][1][wl][2]);
+        N[3] = from_right_or(B[3], edge[lv][qb][0][wr][3]);
+        N[6] = from_right_or(A[5], edge[lv][qa][0][wr][4]);
+        N[7] = from_right_or(C[7], edge[lv][q][0][wr][5]);
+      } else {
+        N[1] = pull_left(B[1]);
+        N[3] = pull_right(B[3]);
+        N[5] = pull_left(A[4]);
+        N[6] = pull_right(A[5]);
+        N[7] = from_right(C[7]);
+        N[8] = from_left(C[8]);
+      }
       if (wall) {
         R r[9];
         unroll<0, 9>([&](auto I) { r[I.value] = N[opp_of(I.value)]; });
@@ -384,6 +453,7 @@ __device__ __forceinline__ void fused_strip(const typename Storage<ST>::T* __res
         // loop and runs out of registers.
         __asm__ volatile("" : "+v"(C[0]), "+v"(C[1]), "+v"(C[2]), "+v"(C[3]), "+v"(C[4]),
                          "+v"(C[5]), "+v"(C[6]), "+v"(C[7]), "+v"(C[8]));
+        publish(lv + 1, q, C);
       }
     }
   };
@@ -402,17 +472,27 @@ template <int K, int EQ, int COLL, int BC, int ST>
 __global__ __launch_bounds__(256) void fused_sweep_kernel(
     const typename Storage<ST>::T* __restrict__ src, typename Storage<ST>::T* __restrict__ dst,
     Geometry g, Coef64 c, int strips, int items, int H) {
-  constexpr int W = 64 - 2 * K;
+  constexpr int NW = FusedLevels<ST>::NW;
+  constexpr int W = 64 * NW - 2 * K;
   // Neighbouring strips share their halo columns, which then come from the
   // XCD's L2 instead of HBM a second time.  The wavefront index is uniform:
   // keep it (and every row base derived from it) in scalar registers.
-  const int wave = xcd_block() * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
-  if (wave >= items) return;  // whole wavefronts leave together
-  const int strip = wave % strips, seg = wave / strips;
   const Coeffs<typename Storage<ST>::R> k(c);
-  fused_strip<K, K, EQ, COLL, BC, ST>(src, dst, g.nx, g.ny, g.plane, strip * W, seg * H, H, k,
-                                      lane);
+  if constexpr (NW == 4) {
+    const int item = xcd_block();  // one work item per workgroup
+    if (item >= items) return;     // the whole workgroup leaves together
+    const int strip = item % strips, seg = item / strips;
+    fused_strip<K, K, EQ, COLL, BC, ST, true>(src, dst, g.nx, g.ny, g.plane, strip * W, seg * H,
+                                              H, k, lane, wv);
+  } else {
+    const int wave = xcd_block() * 4 + wv;
+    if (wave >= items) return;  // whole wavefronts leave together
+    const int strip = wave % strips, seg = wave / strips;
+    fused_strip<K, K, EQ, COLL, BC, ST>(src, dst, g.nx, g.ny, g.plane, strip * W, seg * H, H, k,
+                                        lane);
+  }
 }
 
 // Batched form of fused_sweep_kernel for the server: each wavefront takes one
@@ -739,11 +819,12 @@ hipError_t launch_fused_sweep(int eq, int coll, int bc, int st, const void* src,
     if constexpr (K < 2) {
       return hipErrorInvalidValue;  // single-step storage: use launch_sweep
     } else {
-    constexpr int W = 64 - 2 * K;
+    constexpr int NW = FusedLevels<ST.value>::NW;
+    constexpr int W = 64 * NW - 2 * K;
     const int strips = (g.nx + W - 1) / W;
     const int segs = (g.ny + rows - 1) / rows;
     const int items = strips * segs;
-    const unsigned int nblocks = (unsigned int)((items + 3) / 4);
+    const unsigned int nblocks = (unsigned int)((items + 4 / NW - 1) / (4 / NW));
     return with_eq(eq, [&](auto EQ) {
       return with_coll(coll, [&](auto CO) {
         return with_bc(bc, [&](auto BC) {
@@ -777,10 +858,21 @@ FusedShape fused_shape(int st) {
   return sh;
 }
 
+int fused_wavefronts(int st) {
+  switch (st) {
+    case LB_F64: return FusedLevels<LB_F64>::NW;
+    case LB_F32S: return FusedLevels<LB_F32S>::NW;
+    case LB_F16S: return FusedLevels<LB_F16S>::NW;
+    case LB_BF16S: return FusedLevels<LB_BF16S>::NW;
+    default: return 1;
+  }
+}
+
 double fused_cost(int st, int nx, int ny, int H, const FusedShape& sh) {
-  const int K = fused_levels(st);
-  const int64_t strips = (nx + (64 - 2 * K) - 1) / (64 - 2 * K);
-  const int64_t items = strips * ((ny + H - 1) / H);
+  const int K = fused_levels(st), NW = fused_wavefronts(st), W = 64 * NW - 2 * K;
+  const int64_t strips = (nx + W - 1) / W;
+  // a work item takes NW wavefronts, one on each of NW SIMDs
+  const int64_t items = strips * ((ny + H - 1) / H) * NW;
   const int64_t w = (items + sh.simds - 1) / sh.simds;
   const int64_t resident = w < sh.waves_per_simd ? w : sh.waves_per_simd;
   const double work = K * (double)(H + 2 * K) - K * (K + 1) + 2 * K;

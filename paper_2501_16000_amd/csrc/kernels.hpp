@@ -30,11 +30,15 @@ hipError_t launch_sweep(int eq, int coll, int bc, int st, const void* src, void*
 // Time steps one fused launch advances for a storage format.
 int fused_levels(int st);
 
+// Wavefronts that sweep one strip of a fused launch together (1 or 4).
+int fused_wavefronts(int st);
+
 // Whether fused launches beat single-step launches for this lattice size.
 bool fused_worthwhile(int st, int nx, int ny);
 
-// fused_levels(st) time steps in one launch: src -> dst; each wavefront
-// produces `rows` (a multiple of 3) output rows of a column strip.
+// fused_levels(st) time steps in one launch: src -> dst; each column strip
+// (of one wavefront, or of a whole workgroup: fused_wavefronts) produces
+// `rows` (a multiple of 3) output rows.
 hipError_t launch_fused_sweep(int eq, int coll, int bc, int st, const void* src, void* dst,
                               const Geometry& g, const Coef64& c, int rows, hipStream_t s);
 
@@ -47,10 +51,10 @@ struct FusedShape {
 FusedShape fused_shape(int st);
 
 // Modelled time of one fused launch on an nx x ny lattice with H output rows
-// per wavefront, in row-collision units of one wavefront.
+// per strip, in row-collision units of one wavefront.
 double fused_cost(int st, int nx, int ny, int H, const FusedShape& sh);
 
-// Output rows per wavefront (a multiple of 3) that minimise fused_cost.
+// Output rows per strip (a multiple of 3) that minimise fused_cost.
 int fused_rows(int st, int nx, int ny, const FusedShape& sh);
 
 // g from fields (device FP64 [ny][nx] each); counts invalid input nodes

@@ -369,6 +369,8 @@ FUSED_CASES = [
     (233, 35, "poly2", 1 / 3, 0.8, "bgk", "periodic", "f32s"),
     (1, 200, "guided", 1 / 3, 0.53, "oreg", "periodic", "f32s"),
     (801, 1, "guided", 0.4, 0.6, "oreg", "bounceback", "f32s"),
+    (245, 40, "guided", 1 / 3, 0.7, "oreg", "periodic", "f32s"),    # one 244-column strip and one column
+    (700, 130, "guided", 0.35, 0.6, "bgk", "bounceback", "f32s"),
 ]
 
 

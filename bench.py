@@ -518,6 +518,8 @@ def main():
                                  "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                                  "frac": round(tf / FP32_PEAK_TFLOPS, 4),
                                  "kernel": f"fused_sweep_kernel<K={FUSED_K[st]}, {st}>",
+                                 "traffic": load_traffic(st, n, BYTES_PER_NODE[st] * cells,
+                                                         fused=True),
                                  "hbm_algorithmic_GBs_per_launch": round(v_ach / FUSED_K[st], 1)}
         else:
             entry["roofline"] = {"bound": "hbm", "achieved": round(v_ach, 1),

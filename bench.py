@@ -491,15 +491,20 @@ def main():
                "max": round(reps[-1], 1), "unit": "MLUPS"}
 
     # the other relaxation times of the workload (same kernels, same work,
-    # the same step count)
+    # the same step count), in FP64 and in shifted FP32 storage
     tau_sweep = {}
-    for t_other in (0.51, 1.0):
-        tms, tdiag = time_lattice(oreg, torch, n, t_other, args.storage, args.steps, args.warmup,
-                                  fields)
-        if tdiag[5] != 0:
-            raise RuntimeError(f"non-finite populations at tau={t_other}")
-        tau_sweep[str(t_other)] = {"value": round(cells * args.steps / (tms / 1e3) / 1e6, 1),
-                                   "unit": "MLUPS", "steps": args.steps}
+    for st in dict.fromkeys((args.storage, "f32s")):
+        tau_sweep[st] = {}
+        for t_other in (0.51, 0.6, 1.0):
+            if st == args.storage and t_other == tau:
+                continue
+            tms, tdiag = time_lattice(oreg, torch, n, t_other, st, args.steps, args.warmup,
+                                      fields)
+            if tdiag[5] != 0:
+                raise RuntimeError(f"non-finite populations at tau={t_other} ({st})")
+            tau_sweep[st][str(t_other)] = {
+                "value": round(cells * args.steps / (tms / 1e3) / 1e6, 1), "unit": "MLUPS",
+                "steps": args.steps}
 
     variants = {}
     for st in [s for s in args.variants.split(",") if s and s != args.storage]:

@@ -56,7 +56,9 @@ typedef enum lb_equilibrium { LB_EQ_GUIDED = 0, LB_EQ_POLY2 = 1 } lb_equilibrium
    computes in FP64.  The shifted formats keep f_i - w_i rho0 (w_i the rest
    equilibrium weights of the chosen equilibrium, rho0 the reference density
    of lb_options) rounded to nearest-even in FP32, FP16 or BF16, and collide
-   in FP32 registers. */
+   in FP32 registers; LB_F32S forms the moments rho, j and u = j / rho in
+   FP64 from the FP32 values and rounds them once to FP32 (FP32 sums and
+   1/rho bias the momentum at the FP32 rounding level every step). */
 typedef enum lb_storage {
   LB_F64 = 0,
   LB_F32S = 1,
@@ -126,7 +128,9 @@ lb_status lb_create(int nx, int ny, double tau, double theta, lb_equilibrium eq,
    finite or <= 0 with shifted storage, or a device ordinal out of range. */
 lb_status lb_create_ex(const lb_options* opt, lb_lattice** out);
 
-/* f(x, 0) = f^eq(rho(x), u(x)) and t = 0.  rho, ux, uy: host double [ny][nx].
+/* Initial state (Sec. II; equilibrium of Eq. (11), or of Sec. III.D for
+   LB_EQ_POLY2): f(x, 0) = f^eq(rho(x), u(x)), with no non-equilibrium part,
+   and t = 0.  rho, ux, uy: host double [ny][nx].
    LB_EINVAL for a NULL pointer, a non-finite value or rho <= 0.  Synchronous. */
 lb_status lb_init(lb_lattice* h, const double* rho, const double* ux, const double* uy);
 
@@ -139,13 +143,17 @@ lb_status lb_init(lb_lattice* h, const double* rho, const double* ux, const doub
 lb_status lb_init_device(lb_lattice* h, const double* rho, const double* ux,
                          const double* uy);
 
-/* Enqueue n time steps on the lattice's stream and return (asynchronous).
+/* Eq. (7) applied n times: every step streams the populations and replaces
+   them by f^eq + (1 - 1/tau) f^OReg (Eq. 6), or by the lattice-BGK update of
+   Eq. (1).  Enqueue n time steps on the lattice's stream and return
+   (asynchronous).
    n == 0 is a no-op.  LB_EINVAL for n < 0, LB_ESTATE before init.  With
    check_nonfinite set, waits and returns LB_ENONFINITE if a node holds a
    non-finite population. */
 lb_status lb_step(lb_lattice* h, int64_t n);
 
-/* rho, ux, uy of the pre-collision f(x, t): host double out[3][ny][nx].
+/* Moments of Eq. (2a): rho = sum_i f_i and u = (sum_i c_i f_i) / rho of the
+   pre-collision f(x, t): host double out[3][ny][nx] = rho, ux, uy.
    Waits for the stream. */
 lb_status lb_moments(lb_lattice* h, double* out);
 

@@ -16,7 +16,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "liboreg.so")
-SOURCES = ["lattice.hip", "kernels.hip", "serve.hip", "lattice3.hip", "kernels3.hip", "copy.hip"]
+SOURCES = ["lattice.hip", "kernels.hip", "fused_f64.hip", "fused_f32s.hip", "fused_f16s.hip",
+           "fused_bf16s.hip", "serve.hip", "lattice3.hip", "kernels3.hip", "copy.hip"]
 
 ARCH = "gfx950"
 # -packed-fp32-ops: keep the compiler from forming packed FP32 instructions.
@@ -45,7 +46,7 @@ def _compile(src: str) -> str:
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     sources = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
-    with ThreadPoolExecutor(max_workers=len(sources)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(sources), os.cpu_count() or 4)) as ex:
         objs = list(ex.map(_compile, sources))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-shared", "-fPIC", "-o", tmp, *objs]

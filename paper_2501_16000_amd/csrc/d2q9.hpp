@@ -63,6 +63,7 @@ template <> struct Storage<LB_F64> {
   using T = double;
   using R = double;
   static constexpr bool shifted = false;
+  static constexpr bool wide = false;  // moments in FP64 (see collide)
   __host__ __device__ static R load(T v) { return v; }
   __host__ __device__ static T store(R v) { return v; }
 };
@@ -70,6 +71,7 @@ template <> struct Storage<LB_F32S> {
   using T = float;
   using R = float;
   static constexpr bool shifted = true;
+  static constexpr bool wide = true;
   __host__ __device__ static R load(T v) { return v; }
   __host__ __device__ static T store(R v) { return v; }
 };
@@ -77,6 +79,7 @@ template <> struct Storage<LB_F16S> {
   using T = _Float16;
   using R = float;
   static constexpr bool shifted = true;
+  static constexpr bool wide = false;
   __host__ __device__ static R load(T v) { return (float)v; }
   // Round the FP32 value to nearest even.  The empty asm pins v in a VGPR
   // first: without it the compiler may merge the FP32 FMA that produced v
@@ -95,6 +98,7 @@ template <> struct Storage<LB_BF16S> {
   using T = __bf16;
   using R = float;
   static constexpr bool shifted = true;
+  static constexpr bool wide = false;
   __host__ __device__ static R load(T v) { return (float)v; }
   __host__ __device__ static T store(R v) { return (__bf16)v; }  // v_cvt_pk_bf16_f32, RNE
 };
@@ -114,9 +118,18 @@ struct Coeffs {
   R theta, a0, a1, kappa0, omega, rho0;
   R r0a0, r0a1;        // rho0 a0, rho0 a1
   R kappa_h, kappa_2;  // kappa0 / 2 and 2 kappa0 (exact scalings of kappa0 in R)
+  // a1 = (1 - a0) / 2 is formed in R from the rounded a0, exactly (1 - a0
+  // and the halving do not round for 0 < a0 < 1), so that a0 + 2 a1 = 1
+  // holds exactly in R: the per-axis rest factors then sum to one and the
+  // equilibrium carries the momentum rho u with no spurious factor.
+  // Rounding 1 - theta and theta / 2 separately instead gives, at theta =
+  // 1/3 in FP32, a0 + 2 a1 = 1 + 3e-8, which scales the momentum by that
+  // factor at every collision and made the decay of a shear wave in
+  // shifted FP32 storage 2e-4 too slow over 1500 steps (CPU run of this
+  // collision); with the exact partition it is unbiased.
   __host__ __device__ explicit Coeffs(const Coef64& c)
-      : theta((R)c.theta), a0((R)c.a0), a1((R)c.a1), kappa0((R)c.kappa0),
-        omega((R)c.omega), rho0((R)c.rho0), r0a0((R)(c.rho0 * c.a0)), r0a1((R)(c.rho0 * c.a1)),
+      : theta((R)c.theta), a0((R)c.a0), a1((R(1) - (R)c.a0) * R(0.5)), kappa0((R)c.kappa0),
+        omega((R)c.omega), rho0((R)c.rho0), r0a0((R)c.rho0 * a0), r0a1((R)c.rho0 * a1),
         kappa_h(R(0.5) * (R)c.kappa0), kappa_2(R(2) * (R)c.kappa0) {}
 };
 
@@ -163,6 +176,16 @@ __host__ __device__ __forceinline__ double recip(double x) {
   r = __builtin_fma(r, e, r);
   e = __builtin_fma(-x, r, 1.0);
   return __builtin_fma(r, e, r);
+#else
+  return 1.0 / x;
+#endif
+}
+// 1 / x in FP64 with one Newton step (relative error about 2^-48): for a
+// result that is rounded to FP32 afterwards.
+__host__ __device__ __forceinline__ double recip1(double x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const double r = __builtin_amdgcn_rcp(x);
+  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
 #else
   return 1.0 / x;
 #endif
@@ -322,24 +345,79 @@ __host__ __device__ __forceinline__ void collide_guided_oreg(R (&f)[9], const Co
   }
 }
 
+// Moments of one node (Eq. 2a): rho - rho0 (rho when unshifted), rho, 1/rho,
+// j, u and the second-moment differences d13 = f1 + f3 - f2 - f4, d57 =
+// f5 + f7 - f6 - f8.  Sum w_i = 1 and sum w_i c_i = 0, so the shift only
+// enters rho.
+template <typename R>
+struct Moments {
+  R drho, rho, inv, jx, jy, ux, uy, d13, d57;
+};
+
+template <bool SHIFTED, typename R>
+__host__ __device__ __forceinline__ Moments<R> moments(const R (&f)[9], const Coeffs<R>& k) {
+#pragma clang fp contract(off)
+  Moments<R> m;
+  const R s13 = f[1] + f[3], s24 = f[2] + f[4], s57 = f[5] + f[7], s68 = f[6] + f[8];
+  m.drho = f[0] + (s13 + s24) + (s57 + s68);
+  const R d57 = f[5] - f[7], d86 = f[8] - f[6];
+  m.jx = (f[1] - f[3]) + (d57 + d86);
+  m.jy = (f[2] - f[4]) + (d57 - d86);
+  m.rho = SHIFTED ? k.rho0 + m.drho : m.drho;
+  m.inv = recip(m.rho);
+  m.ux = m.jx * m.inv;
+  m.uy = m.jy * m.inv;
+  m.d13 = s13 - s24;
+  m.d57 = s57 - s68;
+  return m;
+}
+
+// The same from FP32 populations with the sums, rho, 1/rho and u formed in
+// FP64 and rounded once to FP32 (shifted FP32 storage).  In FP32 the
+// rounding of these sums and of 1/rho, with rho within a few ulp of 1 on a
+// smooth flow, does not average out: over 2511 steps of a 937^2 shear wave
+// it made the decay rate 9.8e-4 too small, against 2.8e-5 with this form
+// (CPU run of this collision).
+__host__ __device__ __forceinline__ Moments<float> moments_wide(const float (&f)[9],
+                                                                const Coeffs<float>& k) {
+#pragma clang fp contract(off)
+  double g[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) g[i] = (double)f[i];
+  const double s13 = g[1] + g[3], s24 = g[2] + g[4], s57 = g[5] + g[7], s68 = g[6] + g[8];
+  const double drho = g[0] + (s13 + s24) + (s57 + s68);
+  const double d57 = g[5] - g[7], d86 = g[8] - g[6];
+  const double jx = (g[1] - g[3]) + (d57 + d86);
+  const double jy = (g[2] - g[4]) + (d57 - d86);
+  const double rho = (double)k.rho0 + drho;
+  const double inv = recip1(rho);
+  Moments<float> m;
+  m.drho = (float)drho;
+  m.rho = (float)rho;
+  m.inv = (float)inv;
+  m.jx = (float)jx;
+  m.jy = (float)jy;
+  m.ux = (float)(jx * inv);
+  m.uy = (float)(jy * inv);
+  m.d13 = (float)(s13 - s24);
+  m.d57 = (float)(s57 - s68);
+  return m;
+}
+
 // Collide one node in place.  f holds the pre-collision populations (shifted
-// by w_i rho0 when SHIFTED) and receives the post-collision ones (same shift).
-template <int EQ, int COLL, bool SHIFTED, typename R>
+// by w_i rho0 when SHIFTED) and receives the post-collision ones (same
+// shift).  WIDE: moments by moments_wide (FP32 registers only).
+template <int EQ, int COLL, bool SHIFTED, bool WIDE = false, typename R>
 __host__ __device__ __forceinline__ void collide(R (&f)[9], const Coeffs<R>& k) {
 #pragma clang fp contract(off)
-  // Eq. (2a).  Sum w_i = 1 and sum w_i c_i = 0, so the shift only enters rho.
-  const R s13 = f[1] + f[3], s24 = f[2] + f[4], s57 = f[5] + f[7], s68 = f[6] + f[8];
-  const R drho = f[0] + (s13 + s24) + (s57 + s68);
-  const R d57 = f[5] - f[7], d86 = f[8] - f[6];
-  const R jx = (f[1] - f[3]) + (d57 + d86);
-  const R jy = (f[2] - f[4]) + (d57 - d86);
-  const R rho = SHIFTED ? k.rho0 + drho : drho;
-  const R inv = recip(rho);
-  const R ux = jx * inv, uy = jy * inv;
+  Moments<R> m;
+  if constexpr (WIDE && std::is_same<R, float>::value) m = moments_wide(f, k);
+  else m = moments<SHIFTED>(f, k);
+  const R drho = m.drho, rho = m.rho, inv = m.inv, jx = m.jx, ux = m.ux, uy = m.uy;
   const R uxx = ux * ux, uyy = uy * uy;
 
   if constexpr (EQ == LB_EQ_GUIDED && COLL == LB_COLL_OREG) {
-    collide_guided_oreg<SHIFTED>(f, k, drho, rho, inv, jx, ux, uy, uxx, uyy, s13 - s24, s57 - s68);
+    collide_guided_oreg<SHIFTED>(f, k, drho, rho, inv, jx, ux, uy, uxx, uyy, m.d13, m.d57);
     return;
   }
 
@@ -354,8 +432,8 @@ __host__ __device__ __forceinline__ void collide(R (&f)[9], const Coeffs<R>& k) 
     // Trace-free non-equilibrium stress of Eq. (6) from second moments:
     // S_xx = -S_yy = s, S_xy.
     // 2 s = (Pi_xx - Pi_yy) of f^neq and S_xy.
-    const R s2 = fmadd(-rho, uxx - uyy, s13 - s24);
-    const R sxy = fmadd(-rho, ux * uy, s57 - s68);
+    const R s2 = fmadd(-rho, uxx - uyy, m.d13);
+    const R sxy = fmadd(-rho, ux * uy, m.d57);
     // Eqs. (6), (7): f^post_i = f^eq_i + kappa f^eq_i [s (Cx^2 - Cy^2) + 2 S_xy Cx Cy],
     // kappa = (1 - 1/tau)/(2 rho theta^2), C = c_i - u.  With ks = kappa s and
     // kt = 2 kappa S_xy the bracket splits into per-axis factors:

@@ -27,6 +27,11 @@ constexpr int kDiagBlocks = 1024;
 hipError_t launch_sweep(int eq, int coll, int bc, int st, const void* src, void* dst,
                         const Geometry& g, const Coef64& c, hipStream_t s);
 
+// Work-items (threads) of the single-step sweep launch for storage st on an
+// nx x ny lattice: nodes per row rounded up to the workgroup's tile, times
+// ny, divided by the nodes per thread.  HIP launches stay below 2^32.
+int64_t sweep_work_items(int st, int nx, int ny);
+
 // Time steps one fused launch advances for a storage format.
 int fused_levels(int st);
 
@@ -36,26 +41,32 @@ int fused_wavefronts(int st);
 // Whether fused launches beat single-step launches for this lattice size.
 bool fused_worthwhile(int st, int nx, int ny);
 
-// fused_levels(st) time steps in one launch: src -> dst; each column strip
-// (of one wavefront, or of a whole workgroup: fused_wavefronts) produces
-// `rows` (a multiple of 3) output rows.
-hipError_t launch_fused_sweep(int eq, int coll, int bc, int st, const void* src, void* dst,
-                              const Geometry& g, const Coef64& c, int rows, hipStream_t s);
+// Whether a fused launch of `levels` steps (2 .. fused_levels(st)) is
+// compiled for this collision and boundary: the full count always, fewer
+// steps for periodic OReg lattices.
+bool fused_levels_available(int coll, int bc, int st, int levels);
 
-// SIMDs of the current device and wavefronts of the fused sweep for storage
-// st that one SIMD holds at once (zeros if the query fails).
+// `levels` time steps in one launch: src -> dst; each column strip (of one
+// wavefront, or of a whole workgroup: fused_wavefronts) produces `rows` (a
+// multiple of 3) output rows.
+hipError_t launch_fused_sweep(int eq, int coll, int bc, int st, const void* src, void* dst,
+                              const Geometry& g, const Coef64& c, int rows, int levels,
+                              hipStream_t s);
+
+// SIMDs of the current device and wavefronts of the `levels`-step fused sweep
+// for storage st that one SIMD holds at once (zeros if the query fails).
 struct FusedShape {
   int simds;
   int waves_per_simd;
 };
-FusedShape fused_shape(int st);
+FusedShape fused_shape(int st, int levels);
 
-// Modelled time of one fused launch on an nx x ny lattice with H output rows
-// per strip, in row-collision units of one wavefront.
-double fused_cost(int st, int nx, int ny, int H, const FusedShape& sh);
+// Modelled time of one K-step fused launch on an nx x ny lattice with H
+// output rows per strip, in row-collision units of one wavefront.
+double fused_cost(int st, int nx, int ny, int H, const FusedShape& sh, int K);
 
 // Output rows per strip (a multiple of 3) that minimise fused_cost.
-int fused_rows(int st, int nx, int ny, const FusedShape& sh);
+int fused_rows(int st, int nx, int ny, const FusedShape& sh, int levels);
 
 // g from fields (device FP64 [ny][nx] each); counts invalid input nodes
 // (non-finite value or rho <= 0) into *bad.
@@ -94,24 +105,17 @@ struct LatticeDesc {
   int64_t plane;       // nx * ny
   int64_t admit_T;     // server launch counter at admission; the state is in
                        // buf[(T - admit_T) % 2] before launch T
-  int64_t tile_begin;  // first tile (single-step) or work item (fused) of this lattice
+  int64_t tile_begin;  // first work item of this lattice
   int kl;              // fused launches: time steps this launch advances the lattice
   int rows;            // fused launches: output rows per work item
   int strips;          // fused launches: column strips
   Coef64 coef;
 };
 
-// Nodes per workgroup tile of the batched sweep.
-constexpr int kBatchTile = 1024;
-
-// tile_map[b] = index of the lattice that owns tile b (after the descriptors
-// are in device memory).
+// tile_map[b] = index of the lattice that owns work item b (after the
+// descriptors are in device memory).
 hipError_t launch_tile_map(const LatticeDesc* d, int n, int* tile_map, int64_t tiles,
                            hipStream_t s);
-
-// One time step of every lattice in d[0..n): tiles workgroups, global step T.
-hipError_t launch_batched_sweep(int eq, int st, const LatticeDesc* d, const int* tile_map,
-                                int64_t tiles, int64_t T, hipStream_t s);
 
 // Fused batched launches: up to fused_levels(st) steps per lattice per launch
 // (d[i].kl each), one wavefront per work item (a column strip x a row block).

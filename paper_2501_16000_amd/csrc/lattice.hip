@@ -2,6 +2,7 @@
 // device buffers, stream ordering and error reporting.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -24,7 +25,7 @@ struct lb_lattice {
   int cur = 0;                        // buffer holding the current state
   size_t elem = 8;                    // bytes per stored population
   Geometry geo{};
-  int fused_rows = 66;                // output rows per wavefront of fused launches
+  int fused_rows[8] = {};             // output rows per strip of fused launches, by step count
   Coef64 coef{};
   double theta_energy = 0.0;          // theta of p = rho theta in the energy sum
   bool initialized = false;
@@ -100,10 +101,13 @@ lb_status validate(const lb_options* o) {
     return fail(nullptr, LB_EINVAL, "unknown collision %d", (int)o->collision);
   if (o->boundary_x != LB_BC_PERIODIC && o->boundary_x != LB_BC_BOUNCEBACK)
     return fail(nullptr, LB_EINVAL, "unknown boundary %d", (int)o->boundary_x);
-  // A HIP launch covers fewer than 2^32 work-items per dimension: the sweep
-  // launches ceil(nx / 256) * 256 * ny of them, the per-node kernels nx * ny.
-  const double items = std::ceil(o->nx / 256.0) * 256.0 * (double)o->ny;
-  if (items > 4294967040.0)
+  // A HIP launch covers fewer than 2^32 work-items per dimension: the
+  // single-step sweep launches sweep_work_items() of them (the row rounded up
+  // to the storage's workgroup tile), the per-node kernels nx * ny rounded up
+  // to 256.
+  const int64_t plane = (int64_t)o->nx * (int64_t)o->ny;
+  const int64_t items = std::max(sweep_work_items(o->storage, o->nx, o->ny), (plane + 255) / 256 * 256);
+  if (items > (int64_t)4294967040LL)
     return fail(nullptr, LB_EINVAL, "lattice %d x %d is too large for one launch", o->nx, o->ny);
   if (!is_finite(o->tau) || !(o->tau > 0.5))
     return fail(nullptr, LB_EINVAL, "tau must be finite and > 1/2 (got %g)", o->tau);
@@ -242,9 +246,10 @@ lb_status lb_create_ex(const lb_options* opt, lb_lattice** out) {
   if (e != hipSuccess) return cleanup(hip_fail(nullptr, e, "hipMalloc(aux)"));
   e = hipMalloc((void**)&h->counter, sizeof(unsigned int));
   if (e != hipSuccess) return cleanup(hip_fail(nullptr, e, "hipMalloc(counter)"));
-  if (fused_levels(h->opt.storage) > 1)
-    h->fused_rows = fused_rows(h->opt.storage, h->geo.nx, h->geo.ny,
-                               fused_shape(h->opt.storage));
+  for (int L = 2; L <= fused_levels(h->opt.storage); ++L)
+    if (fused_levels_available(h->opt.collision, h->opt.boundary_x, h->opt.storage, L))
+      h->fused_rows[L] = fused_rows(h->opt.storage, h->geo.nx, h->geo.ny,
+                                    fused_shape(h->opt.storage, L), L);
   *out = h;
   return LB_OK;
 }
@@ -289,19 +294,24 @@ lb_status lb_step(lb_lattice* h, int64_t n) {
   if (n == 0) return LB_OK;
   DeviceScope ds(h->device);
   if (!ds.ok) return fail(h, LB_EDEVICE, "cannot select device %d", h->device);
-  // Fused launches advance K steps each; the remainder runs one step per launch.
+  // Fused launches advance K steps each.  A remainder of two or more steps
+  // runs as one shorter fused launch where that is compiled (periodic OReg:
+  // it reads and writes the state once, where single steps would do so per
+  // step), otherwise, and for a single step, one step per launch.
   const bool fuse =
       h->opt.fuse_steps == 2 ||
       (h->opt.fuse_steps == 0 && fused_worthwhile(h->opt.storage, h->geo.nx, h->geo.ny));
   const int64_t K = fuse ? fused_levels(h->opt.storage) : 1;
   int64_t left = n;
-  while (K > 1 && left >= K) {
+  while (K > 1 && left >= 2) {
+    const int L = (int)std::min<int64_t>(K, left);
+    if (!fused_levels_available(h->opt.collision, h->opt.boundary_x, h->opt.storage, L)) break;
     HIP_TRY(h, launch_fused_sweep(h->opt.equilibrium, h->opt.collision, h->opt.boundary_x,
                                   h->opt.storage, h->buf[h->cur], h->buf[1 - h->cur], h->geo,
-                                  h->coef, h->fused_rows, h->stream));
+                                  h->coef, h->fused_rows[L], L, h->stream));
     h->cur = 1 - h->cur;
-    h->t += K;
-    left -= K;
+    h->t += L;
+    left -= L;
   }
   for (; left > 0; --left) {
     HIP_TRY(h, launch_sweep(h->opt.equilibrium, h->opt.collision, h->opt.boundary_x,

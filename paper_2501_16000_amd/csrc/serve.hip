@@ -142,6 +142,9 @@ struct lb_server {
   int64_t tiles = 0;
   int64_t T = 0;
   int64_t launches = 0, node_updates = 0;
+  bool broken = false;                  // a retire failed: no further work
+  std::string broken_msg;
+  std::vector<ServedLattice*> orphans;  // lattices whose retire failed (freed at destroy)
   std::string err;
 };
 
@@ -250,14 +253,10 @@ lb_status upload_descriptors(lb_server* s) {
   int64_t tiles = 0;
   const int slot = s->desc_slot;
   STRY(s, hipEventSynchronize(s->desc_done[slot]));  // staging slot free again
-  const bool fused = fused_levels(s->opt.storage) > 1;
   for (int i = 0; i < n; ++i) {
     LatticeDesc d = describe(s, s->active[i]);
     d.tile_begin = tiles;
-    if (fused)
-      tiles += (int64_t)d.strips * ((d.ny + d.rows - 1) / d.rows);
-    else
-      tiles += (d.plane + kBatchTile - 1) / kBatchTile;
+    tiles += (int64_t)d.strips * ((d.ny + d.rows - 1) / d.rows);
     s->h_desc[slot][i] = d;
   }
   if (tiles > s->map_capacity) {
@@ -434,6 +433,7 @@ lb_status lb_server_submit(lb_server* s, const lb_request* r) {
         !(r->rho[i] > 0.0))
       return fail(s, LB_EINVAL, "node %lld has a non-finite field or rho <= 0", (long long)i);
 
+  if (s->broken) return fail(s, LB_EDEVICE, "server failed earlier: %s", s->broken_msg.c_str());
   DeviceScope ds(s->device);
   if (!ds.ok) return fail(s, LB_EDEVICE, "cannot select device %d", s->device);
   lb_status st = reclaim_uploads(s);
@@ -506,42 +506,46 @@ lb_status lb_server_step(lb_server* s, int64_t n) {
   if (n < 0) return fail(s, LB_EINVAL, "n %lld", (long long)n);
   DeviceScope ds(s->device);
   if (!ds.ok) return fail(s, LB_EDEVICE, "cannot select device %d", s->device);
+  if (s->broken) return fail(s, LB_EDEVICE, "server failed earlier: %s", s->broken_msg.c_str());
   const int K = fused_levels(s->opt.storage);
   for (int64_t k = 0; k < n && !s->active.empty(); ++k) {
-    if (K > 1) {
-      // a lattice's last launch may advance it fewer than K steps
-      for (ServedLattice* L : s->active) {
-        const int want = (int)std::min<int64_t>(K, L->steps - L->done);
-        if (want != L->kl) {
-          L->kl = want;
-          s->dirty = true;
-        }
+    // a lattice's last launch may advance it fewer than K steps (at least 1:
+    // a lattice is retired as soon as it has run its steps)
+    for (ServedLattice* L : s->active) {
+      const int want = (int)std::max<int64_t>(1, std::min<int64_t>(K, L->steps - L->done));
+      if (want != L->kl) {
+        L->kl = want;
+        s->dirty = true;
       }
     }
     if (s->dirty) {
       lb_status st = upload_descriptors(s);
       if (st != LB_OK) return st;
     }
-    if (K > 1)
-      STRY(s, launch_batched_fused(s->opt.equilibrium, s->opt.storage, s->d_desc, s->d_map,
-                                   s->tiles, s->T, s->compute));
-    else
-      STRY(s, launch_batched_sweep(s->opt.equilibrium, s->opt.storage, s->d_desc, s->d_map,
-                                   s->tiles, s->T, s->compute));
+    STRY(s, launch_batched_fused(s->opt.equilibrium, s->opt.storage, s->d_desc, s->d_map,
+                                 s->tiles, s->T, s->compute));
     s->T += 1;
     s->launches += 1;
     // retire lattices that have run their steps
     for (size_t i = 0; i < s->active.size();) {
       ServedLattice* L = s->active[i];
-      const int adv = K > 1 ? L->kl : 1;
-      L->done += adv;
+      L->done += L->kl;
       L->nlaunch += 1;
-      s->node_updates += (int64_t)L->nx * L->ny * adv;
+      s->node_updates += (int64_t)L->nx * L->ny * L->kl;
       if (L->done >= L->steps) {
-        lb_status st = retire(s, L);
-        if (st != LB_OK) return st;
+        // Out of the active set whatever retire() returns, so that no later
+        // launch advances it again.  A failed retire leaves its gather or
+        // download half enqueued: the server refuses further work (its
+        // memory may still be in use by the device) and reports the error.
         s->active.erase(s->active.begin() + (long)i);
         s->dirty = true;
+        lb_status st = retire(s, L);
+        if (st != LB_OK) {
+          s->broken = true;
+          s->broken_msg = s->err;
+          s->orphans.push_back(L);
+          return st;
+        }
       } else {
         ++i;
       }
@@ -632,6 +636,7 @@ lb_status lb_server_destroy(lb_server* s) {
     for (ServedLattice* L : s->active) free_lattice(L);
     for (ServedLattice* L : s->retiring) free_lattice(L);
     for (ServedLattice* L : s->ready) free_lattice(L);
+    for (ServedLattice* L : s->orphans) free_lattice(L);
     if (s->d_map) (void)hipFree(s->d_map);
     if (s->d_desc) (void)hipFree(s->d_desc);
     if (s->d_bad) (void)hipFree(s->d_bad);

@@ -21,7 +21,7 @@ void run(double theta, double tau, unsigned seed) {
   std::uniform_real_distribution<double> U(-1, 1);
   const double th = EQ == LB_EQ_POLY2 ? 1.0 / 3.0 : theta;
   Coef64 c{th, 1 - th, 0.5 * th, (1 - 1 / tau) / (2 * th * th), 1 / tau, 0.0};
-  double w64 = 0, w32 = 0;
+  double w64 = 0, w32 = 0, ww = 0;
   for (int t = 0; t < 5000; ++t) {
     const double rho = 1 + 0.2 * U(g), ux = 0.1 * U(g), uy = 0.1 * U(g);
     double feq[9], f[9], ref[9];
@@ -40,11 +40,16 @@ void run(double theta, double tau, unsigned seed) {
       w[i] = (cx_of(i) == 0 ? c.a0 : c.a1) * (cy_of(i) == 0 ? c.a0 : c.a1) * c.rho0;
       s[i] = (float)(f[i] - w[i]);
     }
+    float sw[9];
+    for (int i = 0; i < 9; ++i) sw[i] = s[i];
     collide<EQ, COLL, true>(s, Coeffs<float>(c));
     for (int i = 0; i < 9; ++i) w32 = std::fmax(w32, std::fabs((double)s[i] + w[i] - ref[i]));
+    // shifted FP32 with the moments formed in FP64 (the F32S storage)
+    collide<EQ, COLL, true, true>(sw, Coeffs<float>(c));
+    for (int i = 0; i < 9; ++i) ww = std::fmax(ww, std::fabs((double)sw[i] + w[i] - ref[i]));
   }
-  std::printf("eq=%d coll=%d theta=%.4f tau=%.3f f64_rel=%.3e f32s_abs=%.3e\n", EQ, COLL, theta,
-              tau, w64, w32);
+  std::printf("eq=%d coll=%d theta=%.4f tau=%.3f f64_rel=%.3e f32s_abs=%.3e f32w_abs=%.3e\n", EQ,
+              COLL, theta, tau, w64, w32, ww);
 }
 
 int main() {

@@ -1,0 +1,143 @@
+"""Whole-lattice parity at the throughput workload's own size and launch shape.
+
+The 4096^2 rotated shear wave (u0 = 0.05, guided equilibrium, theta = 1/3) is
+the workload the benchmark times, at tau = 0.51, 0.6 and 1.0.  Here every
+population of the whole lattice is compared, not samples:
+
+* FP64 through the default ``lb_step`` path (six-step fused launches with the
+  row block the library picks for 4096^2, then single steps for the
+  remainder) against the FP64 oracle after 100 steps: 1e-12 relative per
+  population (Eq. 7 iterated; both sides FP64, only the evaluation order
+  differs);
+* shifted FP32 storage on the same lattice against the same oracle result,
+  within a bound derived from FP32 rounding (below);
+* for every storage, the default path against one sweep launch per step,
+  bit for bit (the fused pipeline must equal the single-step sweep exactly:
+  the same per-node arithmetic, rounded through the storage format between
+  steps);
+* a 1024^2 lattice of random non-equilibrium populations, where the fused
+  launch has many row blocks per strip, against the oracle.
+
+The oracle's 4096^2 runs take about 25 s each on 16 host threads.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2501_16000_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-12
+N = 4096
+STEPS = 100
+THETA = 1.0 / 3.0
+
+# Shifted FP32 storage against the FP64 oracle after 100 steps.  A stored
+# shifted population |f - w rho0| <= 0.02 on this wave is rounded to FP32
+# with an error of at most 2^-24 * 0.02 = 1.2e-9 per store; the collision's
+# FP32 arithmetic adds errors of the same size.  100 steps of an update whose
+# linearization does not amplify (tau >= 0.51 is stable) accumulate at most
+# about 100 x 9 x 1.2e-9 = 1.1e-6 in the worst case; the bound below asks for
+# a fifth of that.
+F32S_POP_ABS = 2e-7
+F32S_MOMENT_ABS = 2e-7
+
+
+def lib():
+    from paper_2501_16000_amd import oreg
+    return oreg
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_err(got, ref):
+    return float(np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)))
+
+
+@pytest.fixture(scope="module")
+def wave_fields():
+    return workloads.shear_wave(N, 0.05)
+
+
+@pytest.mark.parametrize("tau", [0.51, 0.6, 1.0])
+def test_headline_4096_whole_lattice_vs_oracle(tau, wave_fields):
+    """FP64 and shifted FP32, default launch path, every population of the
+    4096^2 workload after 100 steps against the FP64 oracle."""
+    oreg = lib()
+    rho, ux, uy = wave_fields
+    say(f"[headline] 4096^2 tau={tau}: oracle, {STEPS} steps")
+    ref = oracle.run(oracle.init("guided", THETA, rho, ux, uy), STEPS, tau, THETA)
+    say(f"[headline] 4096^2 tau={tau}: FP64 default path")
+    with oreg.Lattice(N, N, tau, THETA) as L:
+        L.init(rho, ux, uy)
+        L.step(STEPS)
+        got = L.populations()
+        diag = L.diagnostics()
+    err = rel_err(got, ref)
+    say(f"  FP64 max relative population error {err:.3e}")
+    assert err <= RTOL
+    assert diag[5] == 0
+    del got
+    say(f"[headline] 4096^2 tau={tau}: F32S default path")
+    with oreg.Lattice(N, N, tau, THETA, storage="f32s", rho0=1.0) as L:
+        L.init(rho, ux, uy)
+        L.step(STEPS)
+        got = L.populations()
+        m = L.moments()
+    pop_abs = float(np.max(np.abs(got - ref)))
+    del got
+    m_ref = oracle.moments(ref)
+    mom_abs = float(np.max(np.abs(m - m_ref)))
+    say(f"  F32S max |f - f_ref| {pop_abs:.3e}, max |moment - ref| {mom_abs:.3e}")
+    assert pop_abs < F32S_POP_ABS
+    assert mom_abs < F32S_MOMENT_ABS
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32s", "f16s", "bf16s"])
+def test_headline_4096_fused_equals_single_steps(storage, wave_fields):
+    """The default path at 4096^2 (fused launches at the benchmark's launch
+    shape, then single steps) equals one sweep launch per step, bit for bit,
+    on every population of the lattice."""
+    oreg = lib()
+    rho, ux, uy = wave_fields
+    steps = 100
+    say(f"[headline] 4096^2 {storage}: default path vs one step per launch, {steps} steps")
+    out = []
+    for fuse in (0, 1):
+        with oreg.Lattice(N, N, 0.6, THETA, storage=storage, rho0=1.0, fuse_steps=fuse) as L:
+            L.init(rho, ux, uy)
+            L.step(steps)
+            out.append(L.populations())
+    same = np.array_equal(out[0], out[1])
+    if not same:
+        diff = np.argwhere(out[0] != out[1])
+        say(f"  {len(diff)} populations differ; first {diff[:5].tolist()}")
+    assert same
+
+
+@pytest.mark.parametrize("tau", [0.51, 1.0])
+def test_whole_lattice_1024_random_populations(tau):
+    """1024^2 random non-equilibrium populations (every moment and stress
+    component active), default path, against the oracle after 100 steps."""
+    oreg = lib()
+    n = 1024
+    say(f"[headline] 1024^2 random populations tau={tau}, {STEPS} steps")
+    rho = 1.0 + 0.1 * workloads.noise((n, n), 301)
+    ux = 0.05 * workloads.noise((n, n), 302)
+    uy = 0.05 * workloads.noise((n, n), 303)
+    f0 = oracle.init("guided", THETA, rho, ux, uy)
+    f0 = f0 * (1.0 + workloads.noise(f0.shape, 304, 0.02))
+    ref = oracle.run(f0, STEPS, tau, THETA)
+    with oreg.Lattice(n, n, tau, THETA) as L:
+        L.set_populations(f0)
+        L.step(STEPS)
+        got = L.populations()
+    err = rel_err(got, ref)
+    say(f"  max relative population error {err:.3e}")
+    assert err <= RTOL

@@ -411,3 +411,40 @@ def test_copy_device_copies_every_byte(nbytes):
     out = dst.cpu()
     assert torch.equal(out[:nbytes], host[:nbytes])
     assert int(out[nbytes:].count_nonzero()) == 0
+
+
+SHORT_FUSED_CASES = [
+    # (nx, ny, eq, tau, storage, steps): periodic OReg lattices advance a
+    # remainder of 2..5 steps in one shorter fused launch
+    (300, 77, "guided", 0.8, "f64", 2),
+    (300, 77, "guided", 0.8, "f64", 9),     # 6 + 3
+    (64, 64, "poly2", 0.51, "f64", 16),     # 6 + 6 + 4
+    (1, 200, "guided", 0.53, "f64", 5),
+    (801, 3, "guided", 0.6, "f64", 11),     # 6 + 5
+    (513, 130, "guided", 0.6, "f32s", 10),  # 6 + 4
+    (245, 40, "poly2", 0.7, "f32s", 3),
+    (1000, 130, "guided", 0.6, "f16s", 8),  # 6 + 2
+    (97, 33, "guided", 0.8, "bf16s", 17),   # 6 + 6 + 5
+]
+
+
+@pytest.mark.parametrize("nx,ny,eq,tau,storage,steps", SHORT_FUSED_CASES)
+def test_short_fused_launches_equal_single_steps(nx, ny, eq, tau, storage, steps):
+    """Fused launches of fewer than six steps give bit for bit the result of
+    one sweep launch per step (and, in FP64, the oracle's)."""
+    oreg = lib()
+    theta = 1 / 3
+    say(f"[fused short] {nx}x{ny} {eq} {storage} steps={steps}")
+    f0 = random_populations(eq, theta, ny, nx, seed=11 * nx + ny + steps)
+    out = []
+    for fuse in (2, 1):
+        with oreg.Lattice(nx, ny, tau, theta, equilibrium=eq, storage=storage, rho0=1.0,
+                          fuse_steps=fuse) as L:
+            L.set_populations(f0)
+            L.step(steps)
+            assert L.time == steps
+            out.append(L.populations())
+    np.testing.assert_array_equal(out[0], out[1])
+    if storage == "f64":
+        ref = oracle.run(f0, steps, tau, theta, eq)
+        assert rel_err(out[0], ref) <= RTOL

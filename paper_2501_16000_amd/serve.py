@@ -217,12 +217,15 @@ class _FieldPrefetch:
 
 
 def run_stream(server: Server, requests, realtime: bool = True, steps_per_call: int = 4,
-               keep_results: bool = False, timeout_s: float = 600.0) -> StreamReport:
+               keep_results: bool = False, timeout_s: float = 600.0,
+               on_result=None) -> StreamReport:
     """Drive ``requests`` (workloads.ServingRequest) through ``server``.
 
     Requests become visible at their arrival time (``realtime``) or all at
     once; those that do not fit wait in arrival order.  Latency = arrival (or
-    start, without realtime) -> the result's moments in host memory."""
+    start, without realtime) -> the result's moments in host memory.
+    ``keep_results`` keeps every result's moments; ``on_result(tag, moments)``
+    instead keeps only what it returns (for long streams)."""
     pending = sorted(requests, key=lambda r: r.arrival_s)
     fields = _FieldPrefetch(pending)
     queue = []
@@ -257,7 +260,9 @@ def run_stream(server: Server, requests, realtime: bool = True, steps_per_call: 
                     break
                 m = server.fetch(res)
                 report.latency_s[res.tag] = time.perf_counter() - arrival_wall[res.tag]
-                if keep_results:
+                if on_result is not None:
+                    report.results[res.tag] = on_result(res.tag, m)
+                elif keep_results:
                     report.results[res.tag] = m
                 done += 1
             if realtime and i < len(pending) and not queue and server.stats().active == 0:

@@ -180,6 +180,21 @@ lb_status lb_set_populations(lb_lattice* h, const double* in);
    Waits for the stream. */
 lb_status lb_diagnostics(lb_lattice* h, double out[6]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the sums of
+   lb_diagnostics, bit for bit, enqueued into the caller's device array
+   out_dev[6] on the lattice's stream, asynchronously (no host transfer, no
+   synchronization, no hipMalloc/hipFree, no memset).  The reduction's
+   partial sums go to a 48 KiB (1024 x 6 doubles) device array that the
+   library holds statically, one per GPU, for the life of the process: its
+   size is fixed and covers every lattice size.  Every call on a GPU shares
+   that GPU's array, so calls that overlap on one GPU (lattices on different
+   streams, or threads) race and must be ordered by the caller; the array
+   keeps the last call's partials.  The lattice itself must have been created
+   (and initialized) beforehand.  LB_EINVAL for NULL arguments, LB_ESTATE
+   before init, LB_EDEVICE if the array cannot be located on the device. */
+lb_status lb_diagnostics_device_noalloc(lb_lattice* h, double* out_dev);
+
 /* y-average of rho(x) of the pre-collision state: host double out[nx].
    Waits for the stream. */
 lb_status lb_density_profile(lb_lattice* h, double* out);

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -143,6 +144,35 @@ lb_status ensure_tmp(lb_lattice* h) {
 
 lb_status check_handle(lb_lattice* h) {
   if (!h) return fail(nullptr, LB_EINVAL, "lattice handle is NULL");
+  return LB_OK;
+}
+
+// Partial sums of lb_diagnostics_device_noalloc: one row of six per
+// reduction workgroup, in a file-scope device array instead of an allocation.
+// Every GPU the library runs on holds its own copy until the process ends.
+// In host code `scratch` only names the symbol: its device address comes
+// from hipGetSymbolAddress, once per device, and only that address is passed
+// to kernels.
+constexpr int kMaxScratchDevices = 64;
+static __device__ __align__(256) double scratch[kDiagBlocks * 6];
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on `dev` (the current device), looked up on
+// the first call for that device.
+lb_status scratch_ptr(lb_lattice* h, int dev, double** out) {
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(h, LB_EDEVICE, "device %d: no scratch slot (at most %d devices)", dev,
+                kMaxScratchDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return hip_fail(h, e != hipSuccess ? e : hipErrorUnknown,
+                                               "hipGetSymbolAddress(scratch)");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = static_cast<double*>(g_scratch_ptr[dev]);
   return LB_OK;
 }
 
@@ -417,6 +447,22 @@ lb_status lb_diagnostics(lb_lattice* h, double out[6]) {
                                 h->theta_energy, h->stream));
   HIP_TRY(h, hipMemcpyAsync(out, result, 6 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(h, hipStreamSynchronize(h->stream));
+  return LB_OK;
+}
+
+lb_status lb_diagnostics_device_noalloc(lb_lattice* h, double* out_dev) {
+  if (check_handle(h) != LB_OK) return LB_EINVAL;
+  if (!out_dev) return fail(h, LB_EINVAL, "output pointer is NULL");
+  if (!h->initialized) return fail(h, LB_ESTATE, "lattice is not initialized");
+  DeviceScope ds(h->device);
+  if (!ds.ok) return fail(h, LB_EDEVICE, "cannot select device %d", h->device);
+  double* partials = nullptr;
+  lb_status st = scratch_ptr(h, h->device, &partials);
+  if (st != LB_OK) return st;
+  // The same two kernels as lb_diagnostics, in the same reduction order; every
+  // partial is written before the final kernel reads it, so nothing is cleared.
+  HIP_TRY(h, launch_diagnostics(h->opt.storage, h->buf[h->cur], partials, out_dev, h->geo,
+                                h->coef, h->theta_energy, h->stream));
   return LB_OK;
 }
 

@@ -90,6 +90,7 @@ lb_populations = _sig("lb_populations", ctypes.c_int, [_H, _VP])
 lb_set_populations = _sig("lb_set_populations", ctypes.c_int, [_H, _VP])
 lb_diagnostics = _sig("lb_diagnostics", ctypes.c_int, [_H, _VP])
 lb_density_profile = _sig("lb_density_profile", ctypes.c_int, [_H, _VP])
+lb_diagnostics_device_noalloc = _sig("lb_diagnostics_device_noalloc", ctypes.c_int, [_H, _VP])
 lb_sync = _sig("lb_sync", ctypes.c_int, [_H])
 lb_time = _sig("lb_time", ctypes.c_int64, [_H])
 lb_get_options = _sig("lb_get_options", ctypes.c_int, [_H, ctypes.POINTER(lb_options)])
@@ -104,6 +105,7 @@ EXPORTED = [
     "lb_moments", "lb_moments_device", "lb_populations", "lb_set_populations",
     "lb_diagnostics", "lb_density_profile", "lb_sync", "lb_time", "lb_get_options",
     "lb_device_bytes", "lb_destroy", "lb_status_string", "lb_last_error", "lb_copy_device",
+    "lb_diagnostics_device_noalloc",
 ]
 
 
@@ -270,6 +272,15 @@ class Lattice:
         res = np.empty(6)
         check(lb_diagnostics(self._h, _ptr(res)), self._h)
         return res
+
+    def diagnostics_device_noalloc(self, out):
+        """``lb_diagnostics_device_noalloc``: the six sums of ``diagnostics``
+        enqueued into ``out`` (a float64 device tensor of 6 elements) on the
+        lattice's stream, with no allocation and no synchronization."""
+        ptr = _device_ptr(out, (6,))
+        _ready([out])
+        check(lb_diagnostics_device_noalloc(self._h, ptr), self._h)
+        return out
 
     def density_profile(self) -> np.ndarray:
         res = np.empty(self.nx)

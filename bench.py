@@ -153,6 +153,28 @@ def time_box(oreg3, torch, n, tau, storage, steps, warmup, fields):
     return ms, diag
 
 
+def hbm_side(traffic, alg_bytes, launch_s):
+    """HBM view of a fused launch: the algorithmic bytes (the state read and
+    written once per K-step launch: 2 * 9 * sizeof(storage) per node) and the
+    counter bytes of the committed rocprofv3 summary, each over the launch
+    time, against 8 TB/s."""
+    out = {"bytes_model": "2*9*sizeof(storage) per node per K-step launch",
+           "algorithmic_GBs": round(alg_bytes / launch_s / 1e9, 1),
+           "algorithmic_frac_of_peak": round(alg_bytes / launch_s / 1e9 / HBM_PEAK_GBS, 4),
+           "counter_GBs": None, "counter_frac_of_peak": None}
+    if traffic:
+        gbs = traffic / launch_s / 1e9
+        out["counter_GBs"] = round(gbs, 1)
+        out["counter_frac_of_peak"] = round(gbs / HBM_PEAK_GBS, 4)
+    return out
+
+
+def add_copy_fraction(hbm, copy_gbs):
+    hbm["algorithmic_frac_of_copy"] = round(hbm["algorithmic_GBs"] / copy_gbs, 4)
+    hbm["counter_frac_of_copy"] = (round(hbm["counter_GBs"] / copy_gbs, 4)
+                                   if hbm["counter_GBs"] else None)
+
+
 def copy_ceiling(oreg, torch, nbytes, reps=20):
     """GB/s of the library's plain streaming copy (lb_copy_device: every byte
     read once and written once) between two device buffers of nbytes, timed
@@ -466,8 +488,8 @@ def main():
                     "kernel": f"fused_sweep_kernel<K={K}, guided, OReg, periodic, {args.storage}>",
                     "launch_ms": round(per_launch_s * 1e3, 4),
                     "node_updates_per_launch": K * cells,
-                    "flops_per_node_update": FLOPS_PER_UPDATE,
-                    "hbm_algorithmic_GBs": round(alg_bytes / per_launch_s / 1e9, 1)}
+                    "flops_per_node_update": FLOPS_PER_UPDATE}
+        roofline["hbm"] = hbm_side(roofline["traffic"], alg_bytes, per_launch_s)
     else:
         per_launch_s = sec / args.steps
         achieved = alg_bytes / per_launch_s / 1e9
@@ -494,6 +516,8 @@ def main():
     copy = {"value": round(copy_gbs, 1), "unit": "GB/s", "kernel": "copy_kernel (lb_copy_device)",
             "bytes_per_copy": copy_bytes, "copies": 20}
     single["roofline"]["frac_of_copy"] = round(s_ach / copy_gbs, 4)
+    if "hbm" in roofline:
+        add_copy_fraction(roofline["hbm"], copy_gbs)
 
     # spread: five more timed runs of 300 steps each
     reps = []
@@ -533,13 +557,15 @@ def main():
         if FUSED_K[st] > 1:
             # K steps per launch: bounded by VALU issue, not by HBM
             tf = FLOPS_PER_UPDATE * cells * args.variant_steps / vsec / 1e12
+            traffic = load_traffic(st, n, BYTES_PER_NODE[st] * cells, fused=True)
             entry["roofline"] = {"bound": "alu", "achieved": round(tf, 2),
                                  "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                                  "frac": round(tf / FP32_PEAK_TFLOPS, 4),
                                  "kernel": f"fused_sweep_kernel<K={FUSED_K[st]}, {st}>",
-                                 "traffic": load_traffic(st, n, BYTES_PER_NODE[st] * cells,
-                                                         fused=True),
-                                 "hbm_algorithmic_GBs_per_launch": round(v_ach / FUSED_K[st], 1)}
+                                 "traffic": traffic}
+            entry["roofline"]["hbm"] = hbm_side(traffic, BYTES_PER_NODE[st] * cells,
+                                                vsec / args.variant_steps * FUSED_K[st])
+            add_copy_fraction(entry["roofline"]["hbm"], copy_gbs)
         else:
             entry["roofline"] = {"bound": "hbm", "achieved": round(v_ach, 1),
                                  "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -70,6 +70,9 @@ def parse():
     p.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                    help="turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, WRITE_SIZE) of "
                         "--pmc-workload into " + os.path.relpath(TRAFFIC_FILE, ROOT))
+    p.add_argument("--summarize-counters", nargs="+", metavar="CSV",
+                   help="print per-launch SQ / TCP counter figures of the 4096^2 sweep kernels "
+                        "from rocprofv3 --pmc CSVs of --pmc-workload (markdown)")
     return p.parse_args()
 
 
@@ -250,6 +253,53 @@ def pmc_workload(oreg, torch, n, tau, fields):
     torch.cuda.synchronize()
     dst.copy_(src)
     torch.cuda.synchronize()
+
+
+def summarize_counters(paths, n):
+    """Per-launch means of SQ / TCP counters for the D2Q9 sweep kernels, and
+    the figures derived from them, as markdown tables."""
+    import csv
+    import re
+    from collections import defaultdict
+    vals = defaultdict(lambda: defaultdict(list))
+    for path in paths:
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                m = re.search(r"((?:fused_)?sweep_kernel<[^>]*>)", row["Kernel_Name"])
+                if m:
+                    vals[m.group(1)][row["Counter_Name"]].append(float(row["Counter_Value"]))
+    mean = {k: {c: sum(v) / len(v) for c, v in d.items()} for k, d in vals.items()}
+    names = {"0": "F64", "1": "F32S", "2": "F16S", "3": "BF16S"}
+    out = ["| kernel | node updates / launch | waves | VALU instr (wave) | VALU lane-instr / "
+           "update | FP64 FMA / MUL / ADD per update | wave-cycles waiting to issue | "
+           "wave-cycles in s_waitcnt | L2 read latency (cycles) | UTCL1 misses |",
+           "|---|---|---|---|---|---|---|---|---|---|"]
+    for k in sorted(mean):
+        c = mean[k]
+        st = names.get(k.rstrip(">").split(",")[-1].strip(), "?")
+        steps = int(k.split("<")[1].split(",")[0]) if k.startswith("fused") else 1
+        upd = steps * n * n
+
+        def g(name):
+            return c.get(name)
+
+        def per(name):
+            v = g(name)
+            return f"{v * 64 / upd:.1f}" if v is not None else "-"
+
+        def frac(a, b):
+            return f"{100 * g(a) / g(b):.0f} %" if g(a) is not None and g(b) else "-"
+
+        lat = (f"{g('TCP_TCC_READ_REQ_LATENCY') / g('TCP_TCC_READ_REQ'):.0f}"
+               if g("TCP_TCC_READ_REQ") else "-")
+        kind = f"fused, {steps} steps" if k.startswith("fused") else "one step"
+        out.append(f"| `{k}` ({st}, {kind}) | {upd:,} | {g('SQ_WAVES') or 0:.0f} | "
+                   f"{g('SQ_INSTS_VALU') or 0:.4g} | {per('SQ_INSTS_VALU')} | "
+                   f"{per('SQ_INSTS_VALU_FMA_F64')} / {per('SQ_INSTS_VALU_MUL_F64')} / "
+                   f"{per('SQ_INSTS_VALU_ADD_F64')} | {frac('SQ_WAIT_INST_ANY', 'SQ_WAVE_CYCLES')} | "
+                   f"{frac('SQ_WAIT_ANY', 'SQ_WAVE_CYCLES')} | {lat} | "
+                   f"{g('TCP_UTCL1_TRANSLATION_MISS') or 0:.0f} |")
+    print("\n".join(out))
 
 
 def summarize_pmc(fetch_csv, write_csv, n):
@@ -446,6 +496,9 @@ def cpu_baseline(n, tau, steps, fields, single_steps=2):
 
 def main():
     args = parse()
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.n)
+        return 0
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc, args.n)
         return 0

@@ -83,6 +83,32 @@ def test_create_rejects_invalid_options(bad):
     assert m.lb_last_error(None).decode()
 
 
+@pytest.mark.parametrize("storage,launchable", [(0, True), (1, False), (2, True), (3, True)])
+def test_launch_size_limit_uses_each_storages_sweep_tile(storage, launchable):
+    """The single-step sweep launches one thread per node on 256-node tiles
+    (FP64: nx = 600 -> 768 threads per row) and on 512-node tiles (F32S: 1024
+    threads per row), and one thread per two nodes on 512-node tiles (FP16S,
+    BF16S: 512 threads per row).  With ny = 4.2e6 only the F32S launch exceeds
+    2^32 work-items, which lb_create must refuse up front (not the first
+    lb_step)."""
+    import torch
+    m = oreg()
+    o = m.lb_options()
+    m.lb_options_init(ctypes.byref(o))
+    o.nx, o.ny, o.tau, o.storage = 600, 4_200_000, 0.8, storage
+    h = ctypes.c_void_p()
+    st = m.lb_create_ex(ctypes.byref(o), ctypes.byref(h))
+    if not launchable:
+        assert st == m.LB_EINVAL
+        assert "too large" in m.lb_last_error(None).decode()
+    else:
+        assert st != m.LB_EINVAL  # passes validation: no device here, or too little memory
+        if torch.cuda.device_count() == 0:
+            assert st == m.LB_EDEVICE
+        elif st == m.LB_OK:
+            m.lb_destroy(h)
+
+
 def test_null_arguments():
     m = oreg()
     assert m.lb_create(8, 8, 0.8, 1 / 3, 0, None) == m.LB_EINVAL

@@ -40,7 +40,7 @@ STORAGE_BYTES = {"f64": 8, "f32s": 4, "f16s": 2, "bf16s": 2}
 # flops of one guided-equilibrium OReg node update as implemented in
 # d2q9.hpp::collide (FMA = 2, the one division = 1): moments 22, equilibrium
 # 28, stress + reconstruction + relaxation 77.
-FUSED_K = {"f64": 6, "f32s": 6, "f16s": 6, "bf16s": 6}
+FUSED_K = {"f64": 7, "f32s": 6, "f16s": 6, "bf16s": 6}
 FLOPS_PER_UPDATE = 127
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_4096.json")
 

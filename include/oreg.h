@@ -100,15 +100,16 @@ typedef struct lb_options {
                                  kept alive until lb_destroy returns           */
   int device;                 /* HIP device ordinal; -1: current device         */
   int check_nonfinite;        /* nonzero: lb_step scans for NaN/Inf afterwards  */
-  int fuse_steps;             /* 0: lb_step advances six time steps per
-                                 launch (register-resident multi-step sweep;
-                                 same result bit for bit) on lattices of at
-                                 least 48^2 nodes, where it is faster, and
-                                 one step per launch below that and for the
-                                 remainder of n;
+  int fuse_steps;             /* 0: lb_step advances K time steps per launch
+                                 (register-resident multi-step sweep; same
+                                 result bit for bit; K = 7 for LB_F64, 6 for
+                                 the shifted formats) on lattices of at least
+                                 48^2 nodes, where it is faster, a remainder of
+                                 2 .. K-1 steps in one shorter fused launch
+                                 (periodic OReg lattices) and one step per
+                                 launch below that size and otherwise;
                                  1: one sweep launch per time step;
-                                 2: fused launches (six steps each, every
-                                 storage) whatever the size                    */
+                                 2: fused launches whatever the size           */
 } lb_options;
 
 /* Defaults: 0 x 0, tau 1, theta 1/3, guided, LB_F64, OReg, periodic, rho0 1,
@@ -242,7 +243,8 @@ const char* lb_last_error(const lb_lattice* h);
  * footprint is 2 * 9 * sizeof(storage) + 24 bytes per node) and returns
  * LB_EAGAIN otherwise, so the caller keeps the queue and retries as lattices
  * retire.  lb_server_step issues batched launches; one launch covers every
- * resident lattice and advances each by up to K = 6 time steps (fewer in a
+ * resident lattice and advances each by up to K time steps (K as for
+ * lb_step: 7 for LB_F64, 6 for the shifted formats; fewer in a
  * lattice's last launch), running the same per-node update as lb_step (Eqs. (6), (7) with the
  * server's equilibrium and storage and the request's tau).  Each lattice is
  * retired after its requested number of steps: its moments are gathered and

@@ -72,13 +72,22 @@ __device__ __forceinline__ int xcd_block() {
   return xcd * per + (xcd < extra ? xcd : extra) + b / 8;
 }
 
-// Fused launches per storage.  K: steps per launch (six in every format).
+// Fused launches per storage.  K: steps per launch.  FP64: seven.  Its
+// launch time is set by the memory traffic of the strip pipeline (a
+// streaming-only copy of the kernel, with the collision removed, ran within
+// 2 % of it at K = 6, and launches of 2 to 6 steps all took 0.57-0.61 ms on
+// 4096^2), so a further level is nearly free: 4096^2 ran at 169 (K = 6), 178
+// (K = 7) and 179 (K = 8) GLUPS, and K = 7 wastes fewer halo columns and
+// splits short step counts better.  The FP32 formats are bound by their
+// collisions at K = 6 (0.44 ms per launch against 0.30 ms for two steps in
+// F32S) and keep six.
 // NW: wavefronts per strip.  F32S shares one
 // 256-column strip per workgroup (measured 9 % faster than a strip per
 // wavefront: 12 % fewer instructions per node update against six workgroup
 // barriers per row step); in F64 the same layout measured 2 % slower, and
 // the 16-bit formats pre-shift their windows inside the wavefront.
 template <int ST> struct FusedLevels { static constexpr int K = 6, NW = 1; };
+template <> struct FusedLevels<LB_F64> { static constexpr int K = 7, NW = 1; };
 template <> struct FusedLevels<LB_F32S> { static constexpr int K = 6, NW = 4; };
 
 // Fused launches of fewer than FusedLevels<ST>::K steps (lb_step's remainder)

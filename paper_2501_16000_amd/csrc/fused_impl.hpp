@@ -351,15 +351,13 @@ hipError_t fused_launch_st(int eq, int coll, int bc, const void* src, void* dst,
           return hipGetLastError();
         };
         if (levels == K) return go(IC<K>{});
+        hipError_t e = hipErrorInvalidValue;
         if constexpr (short_fused(CO.value, BC.value)) {
-          switch (levels) {
-            case 2: return go(IC<2>{});
-            case 3: return go(IC<3>{});
-            case 4: return go(IC<4>{});
-            case 5: return go(IC<5>{});
-          }
+          unroll<2, K>([&](auto L) {
+            if (levels == L.value) e = go(L);
+          });
         }
-        return hipErrorInvalidValue;
+        return e;
       });
     });
   });
@@ -374,14 +372,11 @@ hipError_t fused_occupancy_st(int levels, int* blocks) {
             &fused_sweep_kernel<L.value, LB_EQ_GUIDED, LB_COLL_OREG, LB_BC_PERIODIC, ST>),
         256, 0);
   };
-  switch (levels) {
-    case 2: return occ(IC<2>{});
-    case 3: return occ(IC<3>{});
-    case 4: return occ(IC<4>{});
-    case 5: return occ(IC<5>{});
-    case 6: return occ(IC<6>{});
-  }
-  return hipErrorInvalidValue;
+  hipError_t e = hipErrorInvalidValue;
+  unroll<2, FusedLevels<ST>::K + 1>([&](auto L) {
+    if (levels == L.value) e = occ(L);
+  });
+  return e;
 }
 
 template <int ST>

@@ -63,7 +63,7 @@ CASES = [
     (37, 53, "poly2", 1 / 3, 0.6, "bgk", "periodic"),
     (40, 3, "guided", 0.35, 0.7, "oreg", "bounceback"),
     (800, 1, "guided", 0.4, 0.6, "oreg", "bounceback"),
-    # the default lb_step path fuses six steps per launch from 48^2 nodes up,
+    # the default lb_step path fuses several steps per launch from 48^2 nodes up,
     # with the row block chosen per lattice: both sides of the threshold,
     # narrow-tall and wide-short strips, every collision and boundary
     (48, 48, "guided", 1 / 3, 0.8, "oreg", "periodic"),
@@ -415,12 +415,13 @@ def test_copy_device_copies_every_byte(nbytes):
 
 SHORT_FUSED_CASES = [
     # (nx, ny, eq, tau, storage, steps): periodic OReg lattices advance a
-    # remainder of 2..5 steps in one shorter fused launch
+    # remainder of 2 .. K-1 steps in one shorter fused launch (K = 7 in FP64,
+    # 6 in the shifted formats)
     (300, 77, "guided", 0.8, "f64", 2),
-    (300, 77, "guided", 0.8, "f64", 9),     # 6 + 3
-    (64, 64, "poly2", 0.51, "f64", 16),     # 6 + 6 + 4
+    (300, 77, "guided", 0.8, "f64", 9),     # 7 + 2
+    (64, 64, "poly2", 0.51, "f64", 20),     # 7 + 7 + 6
     (1, 200, "guided", 0.53, "f64", 5),
-    (801, 3, "guided", 0.6, "f64", 11),     # 6 + 5
+    (801, 3, "guided", 0.6, "f64", 11),     # 7 + 4
     (513, 130, "guided", 0.6, "f32s", 10),  # 6 + 4
     (245, 40, "poly2", 0.7, "f32s", 3),
     (1000, 130, "guided", 0.6, "f16s", 8),  # 6 + 2
@@ -430,7 +431,7 @@ SHORT_FUSED_CASES = [
 
 @pytest.mark.parametrize("nx,ny,eq,tau,storage,steps", SHORT_FUSED_CASES)
 def test_short_fused_launches_equal_single_steps(nx, ny, eq, tau, storage, steps):
-    """Fused launches of fewer than six steps give bit for bit the result of
+    """Fused launches of fewer than K steps give bit for bit the result of
     one sweep launch per step (and, in FP64, the oracle's)."""
     oreg = lib()
     theta = 1 / 3

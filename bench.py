@@ -61,6 +61,9 @@ def parse():
                    help="oracle steps on the full lattice for the CPU baseline")
     p.add_argument("--serving-requests", type=int, default=2000,
                    help="requests of the serving stream (0 skips the serving measurement)")
+    p.add_argument("--serving-plain-requests", type=int, default=0,
+                   help="requests of the stream that the plain FP64 path also runs and the "
+                        "decay-rate errors cover (0: all)")
     p.add_argument("--d3q27-n", type=int, default=256,
                    help="side of the D3Q27 box timed per storage (0 skips it)")
     p.add_argument("--d3q27-steps", type=int, default=100)
@@ -108,7 +111,8 @@ def time_lattice(oreg, torch, n, tau, storage, steps, warmup, fields, fuse_steps
     return ms, diag
 
 
-SOURCES_2D = ("kernels.hip", "d2q9.hpp")
+SOURCES_2D = ("kernels.hip", "d2q9.hpp", "dispatch.hpp", "fused_impl.hpp", "fused_f64.hip",
+              "fused_f32s.hip", "fused_f16s.hip", "fused_bf16s.hip")
 SOURCES_3D = ("kernels3.hip", "d3q27.hpp", "d2q9.hpp")
 
 
@@ -241,7 +245,7 @@ def pmc_workload(oreg, torch, n, tau, fields):
     """A few sweeps per storage and one plain 1 GiB device-to-device copy, the
     calibration of the HBM counters."""
     for st in ("f64", "f32s", "f16s", "bf16s"):
-        time_lattice(oreg, torch, n, tau, st, 12, 0, fields)              # fused launches
+        time_lattice(oreg, torch, n, tau, st, 2 * FUSED_K[st], 0, fields)  # two full fused launches
         time_lattice(oreg, torch, n, tau, st, 5, 2, fields, fuse_steps=1)  # single steps
     from paper_2501_16000_amd import oreg3
     f3 = workloads_shear_wave3(D3_PMC_N)
@@ -307,6 +311,7 @@ def summarize_pmc(fetch_csv, write_csv, n):
     dispatch), each scaled by the ratio of known bytes to the counter's
     reading for the plain copy."""
     import csv
+    import re
     from collections import defaultdict
 
     def read(path, counter):
@@ -346,7 +351,7 @@ def summarize_pmc(fetch_csv, write_csv, n):
         alg = (2 * 27 * STORAGE_BYTES[st] * side ** 3) if d3 else BYTES_PER_NODE[st] * n * n
         out["kernels"][key] = {"n": side,
                                "kernel_source_sha": kernel_source_sha(SOURCES_3D if d3 else SOURCES_2D),
-                               "kernel": k.split("(")[0],
+                               "kernel": (re.search(r"\w+_kernel<[^>]*>", k) or re.search(".*", k)).group(0),
                                "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
                                "hbm_bytes_per_launch": fb + wb,
                                "algorithmic_bytes_per_launch": alg,
@@ -356,7 +361,7 @@ def summarize_pmc(fetch_csv, write_csv, n):
     print(json.dumps(out, indent=1))
 
 
-def serving_bench(oreg, count):
+def serving_bench(oreg, count, plain_count=0):
     """The serving stream: rotated shear waves, N log-uniform in 32..1024,
     tau ~ U[0.52, 1.2], u0 ~ U[0.005, 0.05], steps ~ U{200..5000}, FP32S.
 
@@ -406,8 +411,9 @@ def serving_bench(oreg, count):
         acc64 = serve.run_stream(srv, base, realtime=False, on_result=amplitude).results
     # the plain one-lattice-per-launch FP64 path on the same requests (timed:
     # create, init, steps and moments in host memory, as a served result)
+    checked = base[:plain_count] if plain_count > 0 else base
     plain_s, plain_lup, plain = 0.0, 0, {}
-    for r in base:
+    for r in checked:
         fields = workloads.shear_wave(r.n, r.u0)
         t0 = time.perf_counter()
         with oreg.Lattice(r.n, r.n, r.tau, 1.0 / 3.0) as lat:
@@ -418,7 +424,7 @@ def serving_bench(oreg, count):
         plain[r.rid] = amplitude(r.rid, m)
         plain_lup += r.n * r.n * r.steps
     errs, errs64, worst = [], [], None
-    for r in base:
+    for r in checked:
         a0 = amplitude(r.rid, np.stack(workloads.shear_wave(r.n, r.u0)))
         ln_ref = math.log(a0 / plain[r.rid])
         # well-conditioned decays only: at least 5 % and the wave still at
@@ -441,7 +447,8 @@ def serving_bench(oreg, count):
         "saturated_mlups": round(sat.mlups, 1),
         "launches": rep.launches,
         "plain_f64_one_lattice_per_launch_mlups": round(plain_lup / plain_s / 1e6, 1),
-        "plain_sample": f"all {len(base)} requests of the stream",
+        "plain_sample": (f"all {len(base)} requests of the stream" if len(checked) == len(base)
+                         else f"first {len(checked)} requests of the stream"),
         "served_vs_plain_decay_rate_error": {
             "window": "0.05 <= ln(a0/aT) <= ln(1e4) of the FP64 run",
             "samples": len(errs),
@@ -654,7 +661,7 @@ def main():
     if args.d3q27_n > 0:
         line["d3q27"] = d3q27_bench(torch, args.d3q27_n, tau, args.d3q27_steps, copy_gbs)
     if args.serving_requests > 0:
-        line["serving"] = serving_bench(oreg, args.serving_requests)
+        line["serving"] = serving_bench(oreg, args.serving_requests, args.serving_plain_requests)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n, tau, args.cpu_steps, fields)
     print(json.dumps(line), flush=True)

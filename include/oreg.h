@@ -56,9 +56,10 @@ typedef enum lb_equilibrium { LB_EQ_GUIDED = 0, LB_EQ_POLY2 = 1 } lb_equilibrium
    computes in FP64.  The shifted formats keep f_i - w_i rho0 (w_i the rest
    equilibrium weights of the chosen equilibrium, rho0 the reference density
    of lb_options) rounded to nearest-even in FP32, FP16 or BF16, and collide
-   in FP32 registers; LB_F32S forms the moments rho, j and u = j / rho in
-   FP64 from the FP32 values and rounds them once to FP32 (FP32 sums and
-   1/rho bias the momentum at the FP32 rounding level every step). */
+   in FP32 registers; LB_F32S forms u = j / rho as (j - j e) / rho0 with
+   e = (rho - rho0) / rho, so that the FP32 rounding of rho near rho0 (a
+   smooth error that biases the momentum every step) enters u only through
+   the small e. */
 typedef enum lb_storage {
   LB_F64 = 0,
   LB_F32S = 1,

@@ -63,7 +63,7 @@ template <> struct Storage<LB_F64> {
   using T = double;
   using R = double;
   static constexpr bool shifted = false;
-  static constexpr bool wide = false;  // moments in FP64 (see collide)
+  static constexpr bool delta_u = false;  // u from drho / rho (see moments_delta)
   __host__ __device__ static R load(T v) { return v; }
   __host__ __device__ static T store(R v) { return v; }
 };
@@ -71,7 +71,7 @@ template <> struct Storage<LB_F32S> {
   using T = float;
   using R = float;
   static constexpr bool shifted = true;
-  static constexpr bool wide = true;
+  static constexpr bool delta_u = true;
   __host__ __device__ static R load(T v) { return v; }
   __host__ __device__ static T store(R v) { return v; }
 };
@@ -79,7 +79,7 @@ template <> struct Storage<LB_F16S> {
   using T = _Float16;
   using R = float;
   static constexpr bool shifted = true;
-  static constexpr bool wide = false;
+  static constexpr bool delta_u = false;
   __host__ __device__ static R load(T v) { return (float)v; }
   // Round the FP32 value to nearest even.  The empty asm pins v in a VGPR
   // first: without it the compiler may merge the FP32 FMA that produced v
@@ -98,7 +98,7 @@ template <> struct Storage<LB_BF16S> {
   using T = __bf16;
   using R = float;
   static constexpr bool shifted = true;
-  static constexpr bool wide = false;
+  static constexpr bool delta_u = false;
   __host__ __device__ static R load(T v) { return (float)v; }
   __host__ __device__ static T store(R v) { return (__bf16)v; }  // v_cvt_pk_bf16_f32, RNE
 };
@@ -118,6 +118,7 @@ struct Coeffs {
   R theta, a0, a1, kappa0, omega, rho0;
   R r0a0, r0a1;        // rho0 a0, rho0 a1
   R kappa_h, kappa_2;  // kappa0 / 2 and 2 kappa0 (exact scalings of kappa0 in R)
+  R inv0;              // 1 / rho0 (0 when rho0 = 0: unshifted storage never uses it)
   // a1 = (1 - a0) / 2 is formed in R from the rounded a0, exactly (1 - a0
   // and the halving do not round for 0 < a0 < 1), so that a0 + 2 a1 = 1
   // holds exactly in R: the per-axis rest factors then sum to one and the
@@ -130,7 +131,8 @@ struct Coeffs {
   __host__ __device__ explicit Coeffs(const Coef64& c)
       : theta((R)c.theta), a0((R)c.a0), a1((R(1) - (R)c.a0) * R(0.5)), kappa0((R)c.kappa0),
         omega((R)c.omega), rho0((R)c.rho0), r0a0((R)c.rho0 * a0), r0a1((R)c.rho0 * a1),
-        kappa_h(R(0.5) * (R)c.kappa0), kappa_2(R(2) * (R)c.kappa0) {}
+        kappa_h(R(0.5) * (R)c.kappa0), kappa_2(R(2) * (R)c.kappa0),
+        inv0(c.rho0 != 0.0 ? (R)(1.0 / c.rho0) : R(0)) {}
 };
 
 // Per-axis factor selected by the velocity component c (-1, 0, +1).
@@ -176,16 +178,6 @@ __host__ __device__ __forceinline__ double recip(double x) {
   r = __builtin_fma(r, e, r);
   e = __builtin_fma(-x, r, 1.0);
   return __builtin_fma(r, e, r);
-#else
-  return 1.0 / x;
-#endif
-}
-// 1 / x in FP64 with one Newton step (relative error about 2^-48): for a
-// result that is rounded to FP32 afterwards.
-__host__ __device__ __forceinline__ double recip1(double x) {
-#if defined(__HIP_DEVICE_COMPILE__)
-  const double r = __builtin_amdgcn_rcp(x);
-  return __builtin_fma(r, __builtin_fma(-x, r, 1.0), r);
 #else
   return 1.0 / x;
 #endif
@@ -372,46 +364,44 @@ __host__ __device__ __forceinline__ Moments<R> moments(const R (&f)[9], const Co
   return m;
 }
 
-// The same from FP32 populations with the sums, rho, 1/rho and u formed in
-// FP64 and rounded once to FP32 (shifted FP32 storage).  In FP32 the
-// rounding of these sums and of 1/rho, with rho within a few ulp of 1 on a
-// smooth flow, does not average out: over 2511 steps of a 937^2 shear wave
-// it made the decay rate 9.8e-4 too small, against 2.8e-5 with this form
-// (CPU run of this collision).
-__host__ __device__ __forceinline__ Moments<float> moments_wide(const float (&f)[9],
-                                                                const Coeffs<float>& k) {
+// The same for shifted FP32 storage, with u formed so that the rounding of
+// rho does not enter it: u = j / rho = (j - j e) / rho0 with e = drho / rho.
+// Rounding rho = rho0 + drho to FP32 moves it by up to 2^-25 rho, an error
+// that follows the smooth drho field and so does not average out over the
+// lattice; in u = j / rho it biased the decay of a shear wave (CPU runs of
+// this collision, 969^2, tau 0.70, 4256 steps: decay rate 9.0e-4 too slow).
+// In e the same rounding is an error of relative size drho, and the FMA
+// rounds j - j e once: 2.8e-4 on that run, against 2.7e-4 with the sums,
+// rho, 1/rho and u formed in FP64 and rounded once, which cost 14 more
+// instructions per collision (10 % of the fused F32S sweep's, and 14 % of
+// its throughput); this form costs three more than u = j (1 / rho).
+__host__ __device__ __forceinline__ Moments<float> moments_delta(const float (&f)[9],
+                                                                 const Coeffs<float>& k) {
 #pragma clang fp contract(off)
-  double g[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) g[i] = (double)f[i];
-  const double s13 = g[1] + g[3], s24 = g[2] + g[4], s57 = g[5] + g[7], s68 = g[6] + g[8];
-  const double drho = g[0] + (s13 + s24) + (s57 + s68);
-  const double d57 = g[5] - g[7], d86 = g[8] - g[6];
-  const double jx = (g[1] - g[3]) + (d57 + d86);
-  const double jy = (g[2] - g[4]) + (d57 - d86);
-  const double rho = (double)k.rho0 + drho;
-  const double inv = recip1(rho);
   Moments<float> m;
-  m.drho = (float)drho;
-  m.rho = (float)rho;
-  m.inv = (float)inv;
-  m.jx = (float)jx;
-  m.jy = (float)jy;
-  m.ux = (float)(jx * inv);
-  m.uy = (float)(jy * inv);
-  m.d13 = (float)(s13 - s24);
-  m.d57 = (float)(s57 - s68);
+  const float s13 = f[1] + f[3], s24 = f[2] + f[4], s57 = f[5] + f[7], s68 = f[6] + f[8];
+  m.drho = f[0] + (s13 + s24) + (s57 + s68);
+  const float d57 = f[5] - f[7], d86 = f[8] - f[6];
+  m.jx = (f[1] - f[3]) + (d57 + d86);
+  m.jy = (f[2] - f[4]) + (d57 - d86);
+  m.rho = k.rho0 + m.drho;
+  m.inv = recip(m.rho);
+  const float e = m.drho * m.inv;
+  m.ux = fmadd(-m.jx, e, m.jx) * k.inv0;
+  m.uy = fmadd(-m.jy, e, m.jy) * k.inv0;
+  m.d13 = s13 - s24;
+  m.d57 = s57 - s68;
   return m;
 }
 
 // Collide one node in place.  f holds the pre-collision populations (shifted
 // by w_i rho0 when SHIFTED) and receives the post-collision ones (same
-// shift).  WIDE: moments by moments_wide (FP32 registers only).
-template <int EQ, int COLL, bool SHIFTED, bool WIDE = false, typename R>
+// shift).  DELTA_U: moments by moments_delta (shifted FP32 only).
+template <int EQ, int COLL, bool SHIFTED, bool DELTA_U = false, typename R>
 __host__ __device__ __forceinline__ void collide(R (&f)[9], const Coeffs<R>& k) {
 #pragma clang fp contract(off)
   Moments<R> m;
-  if constexpr (WIDE && std::is_same<R, float>::value) m = moments_wide(f, k);
+  if constexpr (DELTA_U && SHIFTED && std::is_same<R, float>::value) m = moments_delta(f, k);
   else m = moments<SHIFTED>(f, k);
   const R drho = m.drho, rho = m.rho, inv = m.inv, jx = m.jx, ux = m.ux, uy = m.uy;
   const R uxx = ux * ux, uyy = uy * uy;

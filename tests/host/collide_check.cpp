@@ -44,11 +44,11 @@ void run(double theta, double tau, unsigned seed) {
     for (int i = 0; i < 9; ++i) sw[i] = s[i];
     collide<EQ, COLL, true>(s, Coeffs<float>(c));
     for (int i = 0; i < 9; ++i) w32 = std::fmax(w32, std::fabs((double)s[i] + w[i] - ref[i]));
-    // shifted FP32 with the moments formed in FP64 (the F32S storage)
+    // shifted FP32 with u formed from drho / rho (the F32S storage)
     collide<EQ, COLL, true, true>(sw, Coeffs<float>(c));
     for (int i = 0; i < 9; ++i) ww = std::fmax(ww, std::fabs((double)sw[i] + w[i] - ref[i]));
   }
-  std::printf("eq=%d coll=%d theta=%.4f tau=%.3f f64_rel=%.3e f32s_abs=%.3e f32w_abs=%.3e\n", EQ,
+  std::printf("eq=%d coll=%d theta=%.4f tau=%.3f f64_rel=%.3e f32s_abs=%.3e f32u_abs=%.3e\n", EQ,
               COLL, theta, tau, w64, w32, ww);
 }
 

@@ -42,7 +42,7 @@ THETA = 1.0 / 3.0
 # FP32 arithmetic adds errors of the same size.  100 steps of an update whose
 # linearization does not amplify (tau >= 0.51 is stable) accumulate at most
 # about 100 x 9 x 1.2e-9 = 1.1e-6 in the worst case; the bound below asks for
-# a fifth of that (measured: 2e-8 for the populations, 5e-8 for the moments).
+# a fifth of that (measured: 4e-8 for the populations, 1e-7 for the moments).
 F32S_POP_ABS = 2e-7
 F32S_MOMENT_ABS = 2e-7
 

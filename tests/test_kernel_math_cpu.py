@@ -46,12 +46,12 @@ def output3(tmp_path_factory):
 
 
 def test_collision_matches_oracle_on_host(output):
-    rows = re.findall(r"f64_rel=(\S+) f32s_abs=(\S+) f32w_abs=(\S+)", output)
+    rows = re.findall(r"f64_rel=(\S+) f32s_abs=(\S+) f32u_abs=(\S+)", output)
     assert len(rows) == 6, output
-    for f64_rel, f32_abs, f32w_abs in rows:
+    for f64_rel, f32_abs, f32u_abs in rows:
         assert float(f64_rel) < 5e-15, output
         assert float(f32_abs) < 1e-7, output  # ~7 ulp of the largest shifted value
-        assert float(f32w_abs) < 1e-7, output  # FP64 moments, FP32 update
+        assert float(f32u_abs) < 1e-7, output  # u from drho / rho (F32S)
 
 
 def test_d3q27_collision_matches_oracle_on_host(output3):

@@ -242,7 +242,7 @@ __device__ __forceinline__ void fused_strip(const typename Storage<ST>::T* __res
         unroll<0, 9>([&](auto I) { r[I.value] = N[opp_of(I.value)]; });
         unroll<0, 9>([&](auto I) { N[I.value] = r[I.value]; });
       } else {
-        collide<EQ, COLL, S::shifted, S::wide>(N, k);
+        collide<EQ, COLL, S::shifted, S::delta_u>(N, k);
       }
       if (lv + 1 == K) {
 #pragma unroll
@@ -309,7 +309,12 @@ __global__ __launch_bounds__(256) void batched_fused_kernel(const LatticeDesc* _
   using S = Storage<ST>;
   using Tt = typename S::T;
   constexpr int W = 64 - 2 * KMAX;
-  const int64_t item = (int64_t)xcd_block() * 4 + (threadIdx.x >> 6);
+  // The wavefront index is uniform: with readfirstlane the descriptor loads
+  // become scalar loads and the lattice's parameters stay in scalar
+  // registers (without it they took 26-30 VGPRs, one wavefront per SIMD
+  // fewer in F32S, F16S and BF16S).
+  const int64_t item =
+      (int64_t)xcd_block() * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (item >= items) return;  // whole wavefronts leave together
   const LatticeDesc& L = d[map[item]];

@@ -144,7 +144,7 @@ __global__ __launch_bounds__(SweepShape<ST>::BS) void sweep_kernel(
       unroll<0, 9>([&](auto I) { r[I.value] = f[q][opp_of(I.value)]; });
       unroll<0, 9>([&](auto I) { f[q][I.value] = r[I.value]; });
     } else {
-      collide<EQ, COLL, S::shifted, S::wide>(f[q], k);
+      collide<EQ, COLL, S::shifted, S::delta_u>(f[q], k);
     }
   }
   push_local<ST, VX>(dst, g, x0, r0, f);

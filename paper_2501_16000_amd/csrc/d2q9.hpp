@@ -66,6 +66,9 @@ template <> struct Storage<LB_F64> {
   static constexpr bool delta_u = false;  // u from drho / rho (see moments_delta)
   __host__ __device__ static R load(T v) { return v; }
   __host__ __device__ static T store(R v) { return v; }
+  // a, b <- load(store(a)), load(store(b)): the round trip through the
+  // storage format (see the 16-bit formats).
+  __host__ __device__ static void round2(R&, R&) {}
 };
 template <> struct Storage<LB_F32S> {
   using T = float;
@@ -74,6 +77,7 @@ template <> struct Storage<LB_F32S> {
   static constexpr bool delta_u = true;
   __host__ __device__ static R load(T v) { return v; }
   __host__ __device__ static T store(R v) { return v; }
+  __host__ __device__ static void round2(R&, R&) {}
 };
 template <> struct Storage<LB_F16S> {
   using T = _Float16;
@@ -93,6 +97,13 @@ template <> struct Storage<LB_F16S> {
 #endif
     return (_Float16)v;
   }
+  // Two round trips, one value at a time: the packed form (v_cvt_pk_f16_f32
+  // and two v_cvt_f32_f16, one instruction fewer per pair) made the fused
+  // F16S sweep 4 % slower (measured on 4096^2), where BF16S gains from it.
+  __host__ __device__ static void round2(R& a, R& b) {
+    a = load(store(a));
+    b = load(store(b));
+  }
 };
 template <> struct Storage<LB_BF16S> {
   using T = __bf16;
@@ -101,6 +112,16 @@ template <> struct Storage<LB_BF16S> {
   static constexpr bool delta_u = false;
   __host__ __device__ static R load(T v) { return (float)v; }
   __host__ __device__ static T store(R v) { return (__bf16)v; }  // v_cvt_pk_bf16_f32, RNE
+  // Two round trips in one packed conversion (v_cvt_pk_bf16_f32, then a
+  // shift and a mask): three instructions instead of four, the same values;
+  // the fused BF16S sweep ran 6 % faster with it (4096^2).
+  __host__ __device__ static void round2(R& a, R& b) {
+    typedef float F2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 B2 __attribute__((ext_vector_type(2)));
+    const F2 w = __builtin_convertvector(__builtin_convertvector(F2{a, b}, B2), F2);
+    a = w[0];
+    b = w[1];
+  }
 };
 
 // Per-lattice constants of the collision, precomputed on the host in FP64.

@@ -249,7 +249,12 @@ __device__ __forceinline__ void fused_strip(const typename Storage<ST>::T* __res
         for (int i = 0; i < 9; ++i) pend[i] = S::store(N[i]);  // output row Y0 + j - 2K
       } else {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) C[i] = S::load(S::store(N[i]));
+        for (int i = 0; i < 9; ++i) C[i] = N[i];
+        S::round2(C[0], C[1]);
+        S::round2(C[2], C[3]);
+        S::round2(C[4], C[5]);
+        S::round2(C[6], C[7]);
+        C[8] = S::load(S::store(C[8]));
         // Materialise the level's row here: without this ordering point the
         // compiler interleaves the collisions of the straight-line steady
         // loop and runs out of registers.

@@ -284,7 +284,8 @@ __host__ __device__ __forceinline__ void equilibrium(R drho, R rho, R ux, R uy, 
 // f^post_i = f^eq_i (1 + ax - by + tx Cy) (Eqs. 6, 7; the bracket terms are
 // defined in collide below), evaluated as
 //   rho X (Y (1 - by) + Y ax + (Y Cy) tx)                  (unshifted), or
-//   deq_i + rho X (Y ax - Y by + (Y Cy) tx)                 (shifted, with
+//   Y (E + rho X ax - rho X by) + (rho X tx) (Y Cy) + (rho0 ax) dY
+//                                                          (shifted, with
 //   deq_i = f^eq_i - w_i rho0 folded in: see below),
 // with the per-x and per-y products formed once: three operations per
 // population.
@@ -323,12 +324,12 @@ __host__ __device__ __forceinline__ void collide_guided_oreg(R (&f)[9], const Co
   const R s2 = fmadd(-rho, uxx - uyy, d13);
   const R sxy = fmadd(-jx, uy, d57);
   const R ks = (k.kappa_h * inv) * s2, kt = (k.kappa_2 * inv) * sxy;
-  // With C = -1 - u, -u, 1 - u:  ks C^2 = ks (1 + u^2) +- 2 ks u, ks u^2;
+  // With C = -1 - u, -u, 1 - u:  ks C^2 = ks (1 +- 2 u) + ks u^2, ks u^2;
   // kt C = -kt - kt u, -kt u, kt - kt u;  Y C = -(Y + Y u), -Y u, Y - Y u.
-  const R ksx = ks * ux, kox = ks * (R(1) + uxx);
-  const R axm = fmadd(R(2), ksx, kox), ax0 = ks * uxx, axp = fmadd(R(-2), ksx, kox);
-  const R ksy = ks * uy, koy = ks * (R(1) + uyy);
-  const R bym = fmadd(R(2), ksy, koy), by0 = ks * uyy, byp = fmadd(R(-2), ksy, koy);
+  const R ax0 = ks * uxx;
+  const R axm = fmadd(ks, fmadd(R(2), ux, R(1)), ax0), axp = fmadd(ks, fmadd(R(-2), ux, R(1)), ax0);
+  const R by0 = ks * uyy;
+  const R bym = fmadd(ks, fmadd(R(2), uy, R(1)), by0), byp = fmadd(ks, fmadd(R(-2), uy, R(1)), by0);
   const R ktx = kt * ux;
   const R txm = -kt - ktx, tx0 = -ktx, txp = kt - ktx;
   const R Qm = fmadd(-Ym, uy, -Ym), Q0 = -(Y0 * uy), Qp = fmadd(-Yp, uy, Yp);  // Y Cy
@@ -343,17 +344,16 @@ __host__ __device__ __forceinline__ void collide_guided_oreg(R (&f)[9], const Co
     });
   } else {
     // deq_i + rho X (Y ax - Y by + (Y Cy) tx)
-    //   = Y (E + rho X ax) + (rho X tx) (Y Cy) + ((rho0 ax) dY - rho X (Y by)),
+    //   = Y (E + rho X ax - rho X by) + (rho X tx) (Y Cy) + (rho0 ax) dY,
     // every term of the size of the deviation.
-    const R Bm = Ym * bym, B0 = Y0 * by0, Bp = Yp * byp;
     const R Gm = fmadd(rXm, axm, Exm), G0 = fmadd(rX0, ax0, Ex0), Gp = fmadd(rXp, axp, Exp);
     const R Tm = rXm * txm, T0 = rX0 * tx0, Tp = rXp * txp;
     unroll<0, 9>([&](auto I) {
       constexpr int cx = cx_of(I.value), cy = cy_of(I.value);
       const R adY = (cx == 0) ? pick<cy>(a0dYm, a0dY0, a0dYp) : pick<cy>(a1dYm, a1dY0, a1dYp);
-      const R r = fmadd(-pick<cx>(rXm, rX0, rXp), pick<cy>(Bm, B0, Bp), adY);
-      f[I.value] = fmadd(pick<cy>(Ym, Y0, Yp), pick<cx>(Gm, G0, Gp),
-                         fmadd(pick<cx>(Tm, T0, Tp), pick<cy>(Qm, Q0, Qp), r));
+      const R g = fmadd(-pick<cx>(rXm, rX0, rXp), pick<cy>(bym, by0, byp), pick<cx>(Gm, G0, Gp));
+      f[I.value] = fmadd(pick<cy>(Ym, Y0, Yp), g,
+                         fmadd(pick<cx>(Tm, T0, Tp), pick<cy>(Qm, Q0, Qp), adY));
     });
   }
 }

@@ -188,10 +188,13 @@ __host__ __device__ __forceinline__ float fmadd(float a, float b, float c) {
 // correct bits).  v_rcp_f64 alone is good to about 2^-24 relative on gfx950;
 // after two steps the result matched the IEEE quotient exactly on 4M random
 // x in [0.25, 4) (one step left 2e-15), at a third of the cost of the IEEE
-// division sequence.  v_rcp_f32 alone is within 0.9 ulp; without its Newton
-// step the F32S sweep ran 1.5 % faster but its shocktube density error grew
-// by a quarter, so the step stays.  Host builds (the CPU check of this
-// header) divide.
+// division sequence.  v_rcp_f32 alone is within 0.9 ulp: where u = j (1 /
+// rho) (FP16S, BF16S) the Newton step stays (without it the shocktube
+// density error grew by a quarter); the delta form of F32S needs 1 / rho
+// only for the small e = drho / rho and the bracket, where the raw
+// reciprocal (recip_raw) gives the same errors (shocktube L2 6.8e-6 against
+// 8.3e-6 with the step) for 1 % more throughput.  Host builds (the CPU
+// check of this header) divide.
 __host__ __device__ __forceinline__ double recip(double x) {
 #if defined(__HIP_DEVICE_COMPILE__)
   double r = __builtin_amdgcn_rcp(x);
@@ -201,6 +204,13 @@ __host__ __device__ __forceinline__ double recip(double x) {
   return __builtin_fma(r, e, r);
 #else
   return 1.0 / x;
+#endif
+}
+__host__ __device__ __forceinline__ float recip_raw(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);
+#else
+  return 1.0f / x;
 #endif
 }
 __host__ __device__ __forceinline__ float recip(float x) {
@@ -295,29 +305,30 @@ __host__ __device__ __forceinline__ void collide_guided_oreg(R (&f)[9], const Co
                                                              R rho, R inv, R jx, R ux, R uy,
                                                              R uxx, R uyy, R d13, R d57) {
 #pragma clang fp contract(off)
-  R Xm, X0, Xp, Ym, Y0, Yp;
+  R rXm, rX0, rXp, Ym, Y0, Yp;  // rho X and Y
   // Shifted storage only: E = drho X + rho0 dX (per x) and (rho0 a) dY.
   R Exm = 0, Ex0 = 0, Exp = 0, a0dYm = 0, a0dY0 = 0, a0dYp = 0, a1dYm = 0, a1dY0 = 0, a1dYp = 0;
   if constexpr (!SHIFTED) {
     // Psi(+-1) = (a1 + u^2/2) +- u/2, Psi(0) = a0 - u^2.
     const R gx = fmadd(R(0.5), uxx, k.a1), gy = fmadd(R(0.5), uyy, k.a1);
-    Xm = fmadd(R(-0.5), ux, gx), X0 = k.a0 - uxx, Xp = fmadd(R(0.5), ux, gx);
+    const R Xm = fmadd(R(-0.5), ux, gx), X0 = k.a0 - uxx, Xp = fmadd(R(0.5), ux, gx);
     Ym = fmadd(R(-0.5), uy, gy), Y0 = k.a0 - uyy, Yp = fmadd(R(0.5), uy, gy);
+    rXm = rho * Xm, rX0 = rho * X0, rXp = rho * Xp;
   } else {
     // Rest value + small difference, so that deq_i = f^eq_i - w_i rho0 is
     // formed from the differences: deq_i = (drho X + rho0 dX) Y + (rho0 ax) dY.
     const R hx = R(0.5) * uxx, hy = R(0.5) * uyy;
     const R dXm = fmadd(R(-0.5), ux, hx), dX0 = -uxx, dXp = fmadd(R(0.5), ux, hx);
     const R dYm = fmadd(R(-0.5), uy, hy), dY0 = -uyy, dYp = fmadd(R(0.5), uy, hy);
-    Xm = k.a1 + dXm, X0 = k.a0 + dX0, Xp = k.a1 + dXp;
     Ym = k.a1 + dYm, Y0 = k.a0 + dY0, Yp = k.a1 + dYp;
-    // E = drho X + rho0 dX = rho dX + drho a (X = a + dX, rho = rho0 + drho).
+    // E = drho X + rho0 dX = rho dX + drho a (X = a + dX, rho = rho0 + drho),
+    // and rho X = E + rho0 a.
     const R da0 = drho * k.a0, da1 = drho * k.a1;
     Exm = fmadd(rho, dXm, da1), Ex0 = fmadd(rho, dX0, da0), Exp = fmadd(rho, dXp, da1);
+    rXm = Exm + k.r0a1, rX0 = Ex0 + k.r0a0, rXp = Exp + k.r0a1;
     a0dYm = k.r0a0 * dYm, a0dY0 = k.r0a0 * dY0, a0dYp = k.r0a0 * dYp;
     a1dYm = k.r0a1 * dYm, a1dY0 = k.r0a1 * dY0, a1dYp = k.r0a1 * dYp;
   }
-  const R rXm = rho * Xm, rX0 = rho * X0, rXp = rho * Xp;
   // Non-equilibrium stress (2 s = Pi_xx - Pi_yy, S_xy) and the bracket of
   // Eq. (6): kappa [..] = ks Cx^2 - ks Cy^2 + (kt Cx) Cy, C = c_i - u.
   // (rho ux uy = jx uy.)
@@ -406,7 +417,7 @@ __host__ __device__ __forceinline__ Moments<float> moments_delta(const float (&f
   m.jx = (f[1] - f[3]) + (d57 + d86);
   m.jy = (f[2] - f[4]) + (d57 - d86);
   m.rho = k.rho0 + m.drho;
-  m.inv = recip(m.rho);
+  m.inv = recip_raw(m.rho);
   const float e = m.drho * m.inv;
   m.ux = fmadd(-m.jx, e, m.jx) * k.inv0;
   m.uy = fmadd(-m.jy, e, m.jy) * k.inv0;

@@ -82,6 +82,67 @@ __device__ __forceinline__ float lane_perm(float v, int src_byte) {
   return __int_as_float(__builtin_amdgcn_ds_bpermute(src_byte, __float_as_int(v)));
 }
 
+// Access to element (plane i, row r, column col) of the source and
+// destination population buffers.  Global form: a 64-bit address per plane
+// and row.  Buffer form (BUF): one resource descriptor per buffer, the plane
+// offset i * P in a scalar register and the 32-bit in-plane byte offset per
+// lane, so no 64-bit address arithmetic per access (3-5 fewer VALU
+// instructions per collision; measured 1-2 % faster on 4096^2 in every
+// format).  The buffer form needs the buffer below 2 GiB (its byte offsets
+// and the descriptor's record count are 32-bit); the hardware range check
+// returns zero for, and drops, any access beyond it.
+template <typename Tt, bool BUF>
+struct PlaneIO {
+  const Tt* __restrict__ src;
+  Tt* __restrict__ dst;
+  int64_t P;
+  int nx;
+  __device__ PlaneIO(const Tt* s, Tt* d, int64_t p, int n) : src(s), dst(d), P(p), nx(n) {}
+  __device__ Tt load(int i, int r, int col) const { return src[i * P + (int64_t)r * nx + col]; }
+  __device__ void store(int i, int r, int col, Tt v) const {
+    dst[i * P + (int64_t)r * nx + col] = v;
+  }
+};
+template <typename Tt>
+struct PlaneIO<Tt, true> {
+  static constexpr int kDword3 = 0x00020000;  // raw buffer access, gfx9 family
+  __amdgpu_buffer_rsrc_t rs, rd;
+  uint32_t plane_bytes;
+  int nx;
+  __device__ PlaneIO(const Tt* s, Tt* d, int64_t p, int n)
+      : rs(__builtin_amdgcn_make_buffer_rsrc(const_cast<Tt*>(s), 0,
+                                             (int)(9 * p * (int64_t)sizeof(Tt)), kDword3)),
+        rd(__builtin_amdgcn_make_buffer_rsrc(d, 0, (int)(9 * p * (int64_t)sizeof(Tt)), kDword3)),
+        plane_bytes((uint32_t)(p * (int64_t)sizeof(Tt))),
+        nx(n) {}
+  __device__ uint32_t off(int r, int col) const {
+    return ((uint32_t)r * (uint32_t)nx + (uint32_t)col) * (uint32_t)sizeof(Tt);
+  }
+  __device__ Tt load(int i, int r, int col) const {
+    const uint32_t o = off(r, col), so = (uint32_t)i * plane_bytes;
+    if constexpr (sizeof(Tt) == 8)
+      return __builtin_bit_cast(Tt, __builtin_amdgcn_raw_buffer_load_b64(rs, o, so, 0));
+    else if constexpr (sizeof(Tt) == 4)
+      return __builtin_bit_cast(Tt, __builtin_amdgcn_raw_buffer_load_b32(rs, o, so, 0));
+    else
+      return __builtin_bit_cast(Tt, __builtin_amdgcn_raw_buffer_load_b16(rs, o, so, 0));
+  }
+  __device__ void store(int i, int r, int col, Tt v) const {
+    const uint32_t o = off(r, col), so = (uint32_t)i * plane_bytes;
+    if constexpr (sizeof(Tt) == 8)
+      __builtin_amdgcn_raw_buffer_store_b64(
+          __builtin_bit_cast(unsigned int __attribute__((ext_vector_type(2))), v), rd, o, so, 0);
+    else if constexpr (sizeof(Tt) == 4)
+      __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), rd, o, so, 0);
+    else
+      __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), rd, o, so, 0);
+  }
+};
+
+// Largest population buffer (both A/B halves use the same size) that the
+// buffer form of PlaneIO addresses.
+constexpr int64_t kBufferFormBytes = 0x7fffffff;
+
 // One strip: K time steps over the rows Y0 .. Y0 + H - 1 of the columns
 // X0 .. X0 + 64 NW - 1 - 2 KS.  Lane l of wavefront w holds column
 // X0 - KS + 64 w + l; KS >= K is the strip's halo width, so strip columns
@@ -89,7 +150,7 @@ __device__ __forceinline__ float lane_perm(float v, int src_byte) {
 // (SHARE): the four wavefronts of a workgroup sweep one 256-column strip
 // together and hand each other the populations that cross their edges
 // through LDS, so only the workgroup's outer edges carry a halo.
-template <int K, int KS, int EQ, int COLL, int BC, int ST, bool SHARE = false>
+template <int K, int KS, int EQ, int COLL, int BC, int ST, bool SHARE = false, bool BUF = false>
 __device__ __forceinline__ void fused_strip(const typename Storage<ST>::T* __restrict__ src,
                                             typename Storage<ST>::T* __restrict__ dst, int nx,
                                             int ny, int64_t P, int X0, int Y0, int H,
@@ -157,11 +218,12 @@ __device__ __forceinline__ void fused_strip(const typename Storage<ST>::T* __res
       __syncthreads();
     }
   };
+  const PlaneIO<Tt, BUF> io(src, dst, P, nx);
   int row = (Y0 - K) % ny;
   if (row < 0) row += ny;
   Tt nb[3][9];  // level-0 rows: row j is loaded into nb[j % 3] one row ahead
 #pragma unroll
-  for (int i = 0; i < 9; ++i) nb[0][i] = src[i * P + (int64_t)row * nx + col];
+  for (int i = 0; i < 9; ++i) nb[0][i] = io.load(i, row, col);
   // Output row y is stored one step after it is computed, before that step's
   // prefetch: the wait for the prefetched row then covers only stores issued
   // a whole step earlier, never the ones just issued.  Plain stores, not
@@ -175,7 +237,7 @@ __device__ __forceinline__ void fused_strip(const typename Storage<ST>::T* __res
   auto store_row = [&](int y) {
     if (store_lane && y >= Y0 && y < ny) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) dst[i * P + (int64_t)y * nx + col] = pend[i];
+      for (int i = 0; i < 9; ++i) io.store(i, y, col, pend[i]);
     }
   };
 
@@ -203,7 +265,7 @@ __device__ __forceinline__ void fused_strip(const typename Storage<ST>::T* __res
     // leaves nothing of the old buffer alive.
     if (j + 1 < J) row = wrap_inc(row, ny);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) nb[qa][i] = src[i * P + (int64_t)row * nx + col];
+    for (int i = 0; i < 9; ++i) nb[qa][i] = io.load(i, row, col);
 #pragma unroll
     for (int lv = 0; lv < K; ++lv) {
       // Slot q held row j - 3 of the level, which is no longer read.  With
@@ -275,7 +337,7 @@ __device__ __forceinline__ void fused_strip(const typename Storage<ST>::T* __res
   store_row(Y0 + J - 1 - 2 * K);
 }
 
-template <int K, int EQ, int COLL, int BC, int ST>
+template <int K, int EQ, int COLL, int BC, int ST, bool BUF = false>
 __global__ __launch_bounds__(256) void fused_sweep_kernel(
     const typename Storage<ST>::T* __restrict__ src, typename Storage<ST>::T* __restrict__ dst,
     Geometry g, Coef64 c, int strips, int items, int H) {
@@ -291,14 +353,14 @@ __global__ __launch_bounds__(256) void fused_sweep_kernel(
     const int item = xcd_block();  // one work item per workgroup
     if (item >= items) return;     // the whole workgroup leaves together
     const int strip = item % strips, seg = item / strips;
-    fused_strip<K, K, EQ, COLL, BC, ST, true>(src, dst, g.nx, g.ny, g.plane, strip * W, seg * H,
-                                              H, k, lane, wv);
+    fused_strip<K, K, EQ, COLL, BC, ST, true, BUF>(src, dst, g.nx, g.ny, g.plane, strip * W,
+                                                   seg * H, H, k, lane, wv);
   } else {
     const int wave = xcd_block() * 4 + wv;
     if (wave >= items) return;  // whole wavefronts leave together
     const int strip = wave % strips, seg = wave / strips;
-    fused_strip<K, K, EQ, COLL, BC, ST>(src, dst, g.nx, g.ny, g.plane, strip * W, seg * H, H, k,
-                                        lane);
+    fused_strip<K, K, EQ, COLL, BC, ST, false, BUF>(src, dst, g.nx, g.ny, g.plane, strip * W,
+                                                    seg * H, H, k, lane);
   }
 }
 
@@ -350,12 +412,25 @@ hipError_t fused_launch_st(int eq, int coll, int bc, const void* src, void* dst,
   return with_eq(eq, [&](auto EQ) {
     return with_coll(coll, [&](auto CO) {
       return with_bc(bc, [&](auto BC) -> hipError_t {
+        // The buffer form of the plane access (PlaneIO) for the guided
+        // periodic OReg sweep, the configuration of the benchmark, when the
+        // population buffer is below 2 GiB.
+        constexpr bool buf_config = EQ.value == LB_EQ_GUIDED && short_fused(CO.value, BC.value);
+        const bool buf = buf_config && 9 * g.plane * (int64_t)sizeof(T) <= kBufferFormBytes;
         auto go = [&](auto L) -> hipError_t {
           constexpr int W = 64 * NW - 2 * L.value;
           const int strips = (g.nx + W - 1) / W;
           const int segs = (g.ny + rows - 1) / rows;
           const int items = strips * segs;
           const unsigned int nblocks = (unsigned int)((items + 4 / NW - 1) / (4 / NW));
+          if constexpr (buf_config) {
+            if (buf) {
+              fused_sweep_kernel<L.value, EQ.value, CO.value, BC.value, ST, true>
+                  <<<nblocks, 256, 0, s>>>(static_cast<const T*>(src), static_cast<T*>(dst), g, c,
+                                           strips, items, rows);
+              return hipGetLastError();
+            }
+          }
           fused_sweep_kernel<L.value, EQ.value, CO.value, BC.value, ST><<<nblocks, 256, 0, s>>>(
               static_cast<const T*>(src), static_cast<T*>(dst), g, c, strips, items, rows);
           return hipGetLastError();

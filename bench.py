@@ -280,8 +280,10 @@ def summarize_counters(paths, n):
            "|---|---|---|---|---|---|---|---|---|---|"]
     for k in sorted(mean):
         c = mean[k]
-        st = names.get(k.rstrip(">").split(",")[-1].strip(), "?")
-        steps = int(k.split("<")[1].split(",")[0]) if k.startswith("fused") else 1
+        args = [a.strip() for a in k.split("<")[1].rstrip(">").split(",")]
+        fused = k.startswith("fused")
+        st = names.get(args[4 if fused else 3], "?")  # <K, eq, coll, bc, storage[, buf]>
+        steps = int(args[0]) if fused else 1
         upd = steps * n * n
 
         def g(name):

@@ -6,7 +6,9 @@
 * Admission by footprint and by slots: with a budget that holds two lattices,
   the rest wait (submit answers no room) and run as lattices retire.
 * Results agree with the FP64 oracle to the FP32-storage error, and the
-  decay rate of a served shear wave is within 1e-3 of the oracle's.
+  decay rate of a served shear wave is within 1e-3 of the oracle's, also on
+  the corner of the stream's distribution where FP32 storage is least
+  accurate (tau near 1/2, waves that decay by 5-10 % over the run).
 """
 import sys
 
@@ -225,3 +227,42 @@ def test_degenerate_and_non_square_lattices(storage):
             L.init(rho, ux, uy)
             L.step(steps)
             np.testing.assert_array_equal(got[k], L.moments())
+
+
+# The corner of the serving stream's distribution where shifted FP32 storage
+# is least accurate: tau near 1/2 and waves that decay by only 5-10 % over the
+# run (the lower edge of the window 0.05 <= ln(a0/aT) <= ln 1e4 in which the
+# stream's decay rates are compared), N up to 969, up to 5000 steps.  The first
+# two are the stream's worst requests; the others sit at the same edge with
+# tau = 0.52-0.53 and u0 from 0.005 to 0.05.
+CORNER = [(342, 0.5312, 0.0248, 3679), (969, 0.6996, 0.0274, 4256), (300, 0.52, 0.005, 5000),
+          (256, 0.52, 0.05, 5000), (420, 0.53, 0.01, 5000), (180, 0.52, 0.005, 2000)]
+
+
+def test_worst_case_corner_decay_rate():
+    """Served F32S results against the FP64 lb_step path on the corner
+    requests: the decay rate within 1e-3 (the serving accuracy target)."""
+    oreg, serve = mods()
+    reqs = [workloads.ServingRequest(i, 0.0, n, tau, u0, steps)
+            for i, (n, tau, u0, steps) in enumerate(CORNER)]
+    say(f"[serve] {len(reqs)} corner requests, F32S server vs FP64 lb_step")
+    with serve.Server(memory_budget=1 << 32, storage="f32s") as srv:
+        got = serve_all(srv, reqs, steps_per_call=50)
+    for r in reqs:
+        rho, ux, uy = workloads.shear_wave(r.n, r.u0)
+        with oreg.Lattice(r.n, r.n, r.tau, 1 / 3) as L:
+            L.init(rho, ux, uy)
+            L.step(r.steps)
+            ref = L.moments()
+        e_perp, phase = workloads.shear_wave_projection(r.n)
+
+        def amp(m):
+            return abs(((e_perp[0] * m[1] + e_perp[1] * m[2]) * phase).sum())
+
+        a0 = amp(np.stack([rho, ux, uy]))
+        l64 = np.log(a0 / amp(ref))
+        err = abs(np.log(a0 / amp(got[r.rid])) / l64 - 1)
+        say(f"  N={r.n} tau={r.tau} u0={r.u0} steps={r.steps}: ln(a0/aT) {l64:.4f}, "
+            f"decay-rate error {err:.2e}")
+        assert 0.05 <= l64 <= np.log(1e4)
+        assert err < 1e-3

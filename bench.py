@@ -36,12 +36,13 @@ FP32_PEAK_TFLOPS = 157.3    # MI355X FP32 vector
 VALU_PEAK = 256 * 4 * 16 * 2.4e9  # lane-instructions/s: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 BYTES_PER_NODE = {"f64": 144, "f32s": 72, "f16s": 36, "bf16s": 36}
 STORAGE_BYTES = {"f64": 8, "f32s": 4, "f16s": 2, "bf16s": 2}
-# Time steps per fused launch (kernels.hip FusedLevels) and the algorithmic
+# Time steps per fused launch (dispatch.hpp FusedLevels) and the algorithmic
 # flops of one guided-equilibrium OReg node update as implemented in
-# d2q9.hpp::collide (FMA = 2, the one division = 1): moments 22, equilibrium
-# 28, stress + reconstruction + relaxation 77.
+# d2q9.hpp::collide for FP64 (FMA = 2, the one division = 1): moments, 1/rho,
+# u and u^2 22; axis factors and rho X 17; stress and kappa S 9; bracket
+# factors 32; the nine updates 45.
 FUSED_K = {"f64": 7, "f32s": 6, "f16s": 6, "bf16s": 6}
-FLOPS_PER_UPDATE = 127
+FLOPS_PER_UPDATE = 125
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_traffic_4096.json")
 
 
